@@ -1,0 +1,171 @@
+"""Pins for the oracle's Zolo-PD / Zolo-SVD (Algorithms 1 and 2 of the paper).
+
+The polar decomposition of a full-rank A = U diag(sigma) V^T is unique:
+Qp = U V^T, H = V diag(sigma) V^T.  The oracle is pinned to that worked case,
+to the per-iteration spectral form of Theorem 2.2 (every iterate is
+U diag(f_k(sigma)) V^T with f_k the composed scalar Zolotarev maps), to the
+equality of the QR form (12) and the inverse form (11), to a 50-digit mpmath
+SVD on tiny matrices, and to special cases with known polar factors.
+"""
+
+import math
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+from oracle import coeffs as zc
+from oracle import zolo as Z
+from paper_1806_06204_amd import workloads as W
+
+BAR = 1e-13   # backward error and orthogonality bar in FP64
+
+
+def test_worked_case_small_config():
+    cfg = W.config_small()
+    A, U, s, V = cfg["A"], cfg["U"], cfg["sigma"], cfg["V"]
+    Qp, H, info = Z.zolo_pd(A, cfg["alpha"], cfg["l"], cfg["r"])
+    assert info["status"] == 0
+    assert info["kinds"] == ["Q", "C", "C"]
+    assert Z.backward_error(A, Qp, H) <= BAR
+    assert Z.orthogonality(Qp) <= BAR
+    H_ex = (V * s) @ V.T
+    assert Z.frob(H - H_ex) / Z.frob(H_ex) <= 1e-12
+    # Qp is well-posed at kappa = 1e8: perturbation ~ kappa * eps.
+    assert Z.frob(Qp - U @ V.T) / math.sqrt(A.shape[1]) <= 1e-8
+    # l sequence of the scalar recursion (Algorithm 1 step 4(c)).
+    assert info["ls"][0] == 1e-8
+    assert info["ls"][1] == pytest.approx(0.232900733, rel=1e-8)
+    assert 1 - info["ls"][2] == pytest.approx(3.99e-5, rel=1e-2)
+
+
+@pytest.mark.parametrize("kappa,tol", [(1e2, 1e-13), (1e4, 1e-11), (1e8, 1e-8)])
+def test_iterates_are_spectral_maps(kappa, tol):
+    # Theorem 2.2: Zhat(X) = U diag(Zhat(sigma_i)) V^T at every step.
+    A, U, s, V = W.svd_matrix(80, 48, kappa, 31, 32)
+    _, _, info = Z.zolo_pd(A, 1.0, 1.0 / kappa, 3, record=True)
+    f = s.copy()
+    for k, X in enumerate(info["iterates"]):
+        if k > 0:
+            co = zc.coefficients(info["ls"][k - 1], 3)
+            f = zc.zhat(f, co["c"], co["mhat"])
+        D = U.T @ X @ V
+        assert np.linalg.norm(D - np.diag(f)) / math.sqrt(48) <= tol, (k, kappa)
+
+
+@pytest.mark.parametrize("r", [1, 2, 5])
+def test_qr_form_equals_inverse_form(r):
+    # Theorem 2.2: eq. (12) (QR of [X; sqrt(c) I]) equals eq. (11).
+    X = W.svd_matrix(50, 30, 10.0, 41, 42)[0]
+    co = zc.coefficients(0.1, r)
+    Xq = Z.qr_step(X, co)
+    Xc = Z.chol_step(X, co)
+    n = X.shape[1]
+    Xi = X.copy()
+    for j in range(r):
+        Xi = Xi + co["a"][j] * X @ np.linalg.inv(X.T @ X + co["c"][2 * j] * np.eye(n))
+    Xi *= co["mhat"]
+    assert np.linalg.norm(Xq - Xc) <= 1e-13
+    assert np.linalg.norm(Xq - Xi) <= 1e-12
+
+
+def mp_polar(A, dps=50):
+    with mp.workdps(dps):
+        M = mp.matrix(A.tolist())
+        U, S, V = mp.svd_r(M)          # M = U diag(S) V (V holds V^T)
+        n = A.shape[1]
+        Uth = U[:, :n] if U.cols > n else U
+        Qp = Uth * V
+        H = V.T * mp.diag(S) * V
+        return (np.array(Qp.tolist(), dtype=float), np.array(H.tolist(), dtype=float))
+
+
+@pytest.mark.parametrize("m,n,seed", [(8, 5, 1), (6, 6, 2), (8, 8, 3), (3, 1, 4)])
+def test_brute_force_mpmath(m, n, seed):
+    A = np.random.default_rng(seed).standard_normal((m, n))
+    Qp, H, info = Z.zolo_pd(A)
+    assert info["status"] == 0
+    Qm, Hm = mp_polar(A)
+    assert np.abs(Qp - Qm).max() <= 1e-12
+    assert np.abs(H - Hm).max() <= 1e-12 * np.abs(Hm).max()
+
+
+def test_special_cases():
+    Q = W.haar(20, 20, 7)
+    Qp, H, _ = Z.zolo_pd(Q, 1.0, 0.9, 2)
+    assert np.allclose(Qp, Q, atol=1e-14) and np.allclose(H, np.eye(20), atol=1e-14)
+    d = np.array([3.0, -1.0, 0.5, -2e-3, 1.5])
+    Qp, H, _ = Z.zolo_pd(np.diag(d))
+    assert np.allclose(Qp, np.diag(np.sign(d)), atol=1e-14)
+    assert np.allclose(H, np.diag(np.abs(d)), atol=1e-14)
+    Qp, H, _ = Z.zolo_pd(2.5 * Q)
+    assert np.allclose(H, 2.5 * np.eye(20), atol=1e-13) and np.allclose(Qp, Q, atol=1e-14)
+    A = W.svd_matrix(30, 20, 1e6, 51, 52)[0]
+    Qp, _, _ = Z.zolo_pd(A, 1.0, 1e-6, 4)
+    Qp2, H2, _ = Z.zolo_pd(Qp)                  # idempotence
+    assert np.linalg.norm(Qp2 - Qp) <= 1e-13 * 20
+    assert np.linalg.norm(H2 - np.eye(20)) <= 1e-13 * 20
+
+
+def test_invariants_and_schedules_kappa_1e16():
+    A, U, s, V = W.svd_matrix(64, 64, 1e16, 11, 12)
+    for r, first in [(8, ["Q", "C"]), (3, ["Q", "Q", "C"])]:
+        Qp, H, info = Z.zolo_pd(A, 1.0, 1e-16, r)
+        assert info["status"] == 0
+        assert info["kinds"][:len(first)] == first
+        assert Z.backward_error(A, Qp, H) <= BAR
+        assert Z.orthogonality(Qp) <= BAR
+        assert np.allclose(H, H.T, atol=0)
+        assert np.linalg.eigvalsh(H).min() >= -64 * 2.2e-16 * np.abs(s).max()
+        H_ex = (V * s) @ V.T
+        assert Z.frob(H - H_ex) / Z.frob(H_ex) <= 1e-13
+
+
+def test_paper_stop_rule():
+    cfg = W.config_small()
+    Qp, H, info = Z.zolo_pd(cfg["A"], 1.0, cfg["l"], 3, stop="paper")
+    assert info["status"] == 0 and info["kinds"] == ["Q", "C", "C"]
+    assert Z.backward_error(cfg["A"], Qp, H) <= BAR
+
+
+def test_estimators_bound_the_spectrum():
+    A, U, s, V = W.svd_matrix(90, 60, 1e5, 61, 62)
+    A = 3.0 * A
+    alpha = Z.estimate_alpha(A)
+    assert alpha >= 3.0 and alpha <= 3.0 * 1.02
+    l = Z.estimate_l(A / alpha)
+    assert l <= 3.0 * s.min() / alpha
+    assert l >= 3.0 * s.min() / alpha / (60 * 10)
+
+
+def test_failure_modes():
+    cfg = W.config_small()
+    _, _, info = Z.zolo_pd(cfg["A"], 1.0, cfg["l"], 3, max_iter=1)
+    assert info["status"] == 1 and info["iters"] == 1
+    A = W.svd_matrix(40, 20, 10.0, 71, 72)[0]
+    A[:, 7] = 0.0                              # exactly rank deficient
+    Qp, _, info = Z.zolo_pd(A, 1.0, 1e-3, 3)
+    assert info["status"] == 1                 # no false success
+    assert Z.orthogonality(Qp) > 1e-2
+    bad = cfg["A"].copy()
+    bad[3, 4] = np.nan
+    with pytest.raises(ValueError):
+        Z.zolo_pd(bad)
+    with pytest.raises(ValueError):
+        Z.zolo_pd(cfg["A"].T)
+
+
+def test_forced_cholesky_breakdown_falls_back_to_qr():
+    A = W.svd_matrix(40, 40, 1e16, 81, 82)[0]
+    Qp, H, info = Z.zolo_pd(A, 1.0, 1e-16, 8, chol_switch=1e300)
+    assert info["chol_fallbacks"] >= 1 and info["kinds"][0] == "Q"
+    assert info["status"] == 0
+    assert Z.backward_error(A, Qp, H) <= BAR
+
+
+def test_svd():
+    A, U, s, V = W.svd_matrix(30, 24, 1e6, 91, 92)
+    Uc, S, Vc, info = Z.zolo_svd(A, 1.0, 1e-6, 4)
+    assert np.allclose(S, s, rtol=1e-10, atol=1e-15)
+    assert Z.svd_residual_paper(A, Uc, S, Vc) <= 1e-13
+    assert Z.orth_paper(Uc) <= 1e-15 and Z.orth_paper(Vc) <= 1e-15
