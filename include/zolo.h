@@ -1,0 +1,156 @@
+/*
+ * zolo.h - C ABI of the MI355X (gfx950) Zolo-PD library.
+ *
+ * The library computes the polar decomposition A = Qp * H of a real m x n
+ * matrix (m >= n): Qp has orthonormal columns and H is symmetric positive
+ * semidefinite (eq. (1) of Li, Liu & Du, arXiv 1806.06204).  It runs the
+ * Zolo-PD iteration of Algorithm 1 (Section 2.2): every step applies the
+ * scaled Zolotarev function of eq. (8) to the iterate X, either through r
+ * independent Householder QRs of the stacked [X; sqrt(c_{2j-1}) I] (eq. (12))
+ * or, once that is safe, through Cholesky factors of X^T X + c_{2j-1} I
+ * (Algorithm 1 step 4(d)), and finally forms H = (Qp^T A + (Qp^T A)^T)/2.
+ * The r factorisations of one step run together in batched GPU kernels.
+ *
+ * Conventions for every call:
+ *   - real FP64, column-major storage, leading dimensions in elements;
+ *   - matrix pointers (A, Qp, H, U, V) are DEVICE pointers, on the GPU that is
+ *     current when the handle was created; S and every scalar array are HOST
+ *     pointers;
+ *   - work is queued on the handle's HIP stream; the calls return once the
+ *     results are complete (each iteration reads one scalar back to the host);
+ *   - the caller owns A, Qp, H, U, S, V; A is never modified; outputs must not
+ *     overlap A;
+ *   - the library owns its device workspace, kept in the handle and grown on
+ *     demand; zolo_destroy releases it;
+ *   - no call prints, throws or aborts.
+ *
+ * Return codes (int):
+ *    0  ZOLO_OK
+ *   -i  the i-th argument is invalid (LAPACK convention, counting from 1)
+ *    1  ZOLO_NOT_CONVERGED: max_iter reached; outputs hold the last iterate
+ *       and info holds the achieved errors
+ *    2  ZOLO_NONFINITE: A holds NaN or Inf
+ *    3  ZOLO_ALLOC: device workspace allocation failed
+ *    4  ZOLO_HIP: a HIP runtime call failed
+ *    5  ZOLO_KERNEL: a kernel reported an internal failure (a cooperative
+ *       barrier that did not complete within its bounded wait)
+ *    6  ZOLO_BREAKDOWN: a factorisation met a non-positive pivot where no
+ *       fallback exists (building-block entry points only)
+ */
+#ifndef ZOLO_H
+#define ZOLO_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ZOLO_OK 0
+#define ZOLO_NOT_CONVERGED 1
+#define ZOLO_NONFINITE 2
+#define ZOLO_ALLOC 3
+#define ZOLO_HIP 4
+#define ZOLO_KERNEL 5
+#define ZOLO_BREAKDOWN 6
+
+#define ZOLO_MAX_R 8
+#define ZOLO_MAX_ITER 16
+
+typedef struct zolo_handle_s* zolo_handle;
+
+/* Options.  Initialise with zolo_default_opts(). */
+typedef struct {
+    int max_iter;        /* iteration limit (default 10, at most ZOLO_MAX_ITER) */
+    int stop_rule;       /* 0 verified (default): once the predicted l reaches
+                            1 - 1e-15, stop when ||X^T X - I||_F / sqrt(n) <= tau,
+                            else continue with l = sqrt(1 - sqrt(n) d);
+                            1 paper: ||X_new - X_old||_F / ||X_new||_F <= eps^(1/(2r+1))
+                            (Algorithm 1 step 4(d), Algorithm 3 step 4(e)) */
+    double tau;          /* verified-stop threshold (default 5e-14) */
+    double chol_switch;  /* QR-type step while (1+c_1)/(l^2+c_1) > chol_switch
+                            (default 100; the QDWH switch of Section 2.1) */
+    int qr_variant;      /* 0 (default): structured QR of [X; sqrt(c) I] with
+                            m + NB live rows per panel (Section 3.1);
+                            1: one Householder QR X = Q_X R_X shared by all j,
+                            then structured QRs of [R_X; sqrt(c) I] */
+    int precision;       /* 0 (default): every step in FP64.  Other values are
+                            rejected (-argument) in this version. */
+    int compute_errors;  /* 1: fill info->bwd_err and info->orth_err (costs two
+                            extra GEMMs); 0 (default): leave them at -1 */
+    int reserved[9];
+} zolo_opts;
+
+/* Per-call report. */
+typedef struct {
+    int status;            /* same value as the return code */
+    int iters;             /* iterations taken */
+    int r_used;            /* Zolotarev degree r */
+    int chol_fallbacks;    /* Cholesky-type steps redone as QR-type */
+    char kind[ZOLO_MAX_ITER + 1];  /* 'Q' or 'C' per iteration, NUL-terminated */
+    double alpha;          /* scaling alpha >= sigma_max(A) used, X0 = A / alpha */
+    double l0;             /* l used for the first step (after clamping) */
+    double l_seq[ZOLO_MAX_ITER];   /* l before each step */
+    double orth_check;     /* last ||X^T X - I||_F / sqrt(n) (verified rule), else -1 */
+    double t_stage[8];     /* milliseconds: [0] scale and estimates, [1] QR-type
+                              steps, [2] Cholesky-type steps, [3] stop checks,
+                              [4] H, [5] eigensolver (zolo_svd), [6] U = Qp V,
+                              [7] whole call */
+    double flops_exec;     /* floating-point operations executed by the kernels */
+    double flops_paper;    /* the paper method's count for the executed schedule:
+                              5 r m n^2 per QR-type step, m n^2 + r (n^3/3 +
+                              2 m n^2) per Cholesky-type step, 2 m n^2 for H,
+                              m n^2 per verified check */
+    double bwd_err;        /* ||A - Qp H||_F / ||A||_F if requested, else -1 */
+    double orth_err;       /* ||Qp^T Qp - I||_F / sqrt(n) if requested, else -1 */
+} zolo_info;
+
+/* Fill *opts with the defaults listed above. */
+void zolo_default_opts(zolo_opts* opts);
+
+/* Create a handle bound to the current HIP device and to `stream` (a
+ * hipStream_t; NULL = the default stream).  Returns 0 or ZOLO_HIP. */
+int zolo_create(zolo_handle* handle, void* stream);
+
+/* Change the stream a handle queues work on. */
+int zolo_set_stream(zolo_handle handle, void* stream);
+
+/* Release the handle and its device workspace. */
+int zolo_destroy(zolo_handle handle);
+
+/* Zolotarev coefficients for lower bound l and degree r (host only, no handle).
+ * Section 2.2: c[0..2r-1] = c_1..c_{2r} of eq. (7); a[0..r-1] = a_1..a_r of
+ * eq. (10) (taken as the quotient that makes the partial-fraction identity (9)
+ * hold); *mhat = Mhat of eq. (8); *l_next = Zhat(l; l), the l-update of
+ * Algorithm 1 step 4(c) (with l^2 + c_{2j} in the numerator).
+ * Any output pointer may be NULL.  l is clamped to >= 1e-20.
+ * Returns 0, -1 if l is not in (0, 1], -2 if r is not in [1, ZOLO_MAX_R]. */
+int zolo_coeffs(double l, int r, double* c, double* a, double* mhat, double* l_next);
+
+/* Zolo-PD, Algorithm 1: A (m x n, lda >= m) -> Qp (m x n, ldq >= m) and
+ * H (n x n, ldh >= n), with m >= n >= 1.
+ *   alpha > 0: used as the upper bound of sigma_max(A) (Algorithm 1 step 1);
+ *              alpha <= 0: estimated as 1.01 x a power-iteration estimate.
+ *   l in (0,1]: lower bound of sigma_min(A/alpha) (step 2);
+ *              l <= 0: estimated as 1/(sqrt(n) ||R^{-1}||_1) from A/alpha = QR.
+ *   r in [1,8]: Zolotarev degree; r <= 0: the smallest r whose scalar
+ *              recursion converges within two steps (step 3, Table 1).
+ * opts may be NULL (defaults).  info may be NULL. */
+int zolo_pd(zolo_handle handle, int m, int n, const double* A, int lda,
+            double alpha, double l, int r,
+            double* Qp, int ldq, double* H, int ldh,
+            const zolo_opts* opts, zolo_info* info);
+
+/* Zolo-SVD, Algorithm 2: A = Qp H by zolo_pd, then H = V diag(S) V^T by a
+ * plain FP64 symmetric eigensolver on the GPU (cyclic Jacobi), then U = Qp V.
+ * U is m x n (ldu >= m), S has n entries (host, descending), V is n x n
+ * (ldv >= n).  The eigensolver and the product are timed in info->t_stage[5]
+ * and [6], apart from the polar decomposition. */
+int zolo_svd(zolo_handle handle, int m, int n, const double* A, int lda,
+             double alpha, double l, int r,
+             double* U, int ldu, double* S, double* V, int ldv,
+             const zolo_opts* opts, zolo_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ZOLO_H */

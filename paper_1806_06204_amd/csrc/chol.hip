@@ -1,0 +1,186 @@
+// Batched upper Cholesky and triangular inverse for the Cholesky-type step of
+// Zolo-PD (Algorithm 1 step 4(d)): Z_j = X^T X + c_{2j-1} I = R_j^T R_j for all
+// j at once, then R_j^{-1}.
+//
+// POTRF is right-looking with 64-column blocks: a 64 x 64 diagonal block is
+// factored in LDS by one workgroup per matrix (which also inverts it), the row
+// panel to its right becomes R_kk^{-T} Z_12 (one GEMM), and the trailing matrix
+// takes the symmetric rank-64 update on its upper tiles (one GEMM).
+//
+// TRTRI is recursive and level-batched: all 64 x 64 diagonal blocks are
+// inverted at once, then for block sizes s = 64, 128, 256, ... every pair of
+// neighbouring s-blocks is merged with two GEMMs,
+//     inv([R11 R12; 0 R22]) = [R11^{-1}, -R11^{-1} R12 R22^{-1}; 0, R22^{-1}],
+// batched over all pairs of a level and all matrices.
+#include "misc.hpp"
+
+namespace zolo {
+namespace {
+
+constexpr int kB = 64;
+
+// Inverse of the upper-triangular kb x kb matrix S (LDS) into Si (LDS):
+// thread j back-substitutes column j.
+__device__ void lds_upper_inverse(int kb, const double (*S)[kB + 1], double (*Si)[kB + 1]) {
+    const int j = threadIdx.x;
+    if (j < kB) {
+        for (int i = kB - 1; i > j; --i) Si[i][j] = 0.0;
+        if (j < kb) {
+            for (int i = j; i >= 0; --i) {
+                double s = (i == j) ? 1.0 : 0.0;
+                for (int k = i + 1; k <= j; ++k) s -= S[i][k] * Si[k][j];
+                Si[i][j] = s / S[i][i];
+            }
+        } else {
+            for (int i = 0; i <= j; ++i) Si[i][j] = (i == j) ? 1.0 : 0.0;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void potrf_diag_kernel(int k0, int kb, double* Z, long long ldz, long long sz,
+                                                         int* info, double* work) {
+    __shared__ double S[kB][kB + 1];
+    __shared__ double Si[kB][kB + 1];
+    __shared__ int s_bad;
+    const int b = blockIdx.x, tid = threadIdx.x;
+    double* Zb = Z + b * sz + k0 + (long long)k0 * ldz;
+    for (int e = tid; e < kB * kB; e += 256) {
+        const int i = e % kB, j = e / kB;
+        S[i][j] = (i < kb && j < kb && i <= j) ? Zb[i + (long long)j * ldz] : 0.0;
+    }
+    if (tid == 0) s_bad = 0;
+    __syncthreads();
+    for (int k = 0; k < kb; ++k) {
+        if (tid == 0) {
+            double d = S[k][k];
+            if (!(d > 0.0) || !isfinite(d)) {
+                if (s_bad == 0) s_bad = k0 + k + 1;
+                d = 1.0;  // keep going so every wave finishes; the caller discards the result
+            }
+            S[k][k] = sqrt(d);
+        }
+        __syncthreads();
+        if (tid > k && tid < kb) S[k][tid] /= S[k][k];
+        __syncthreads();
+        const int w = kb - k - 1;
+        for (int e = tid; e < w * w; e += 256) {
+            const int ii = k + 1 + e % w, jj = k + 1 + e / w;
+            if (ii <= jj) S[ii][jj] -= S[k][ii] * S[k][jj];
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < kb * kb; e += 256) {
+        const int i = e % kb, j = e / kb;
+        Zb[i + (long long)j * ldz] = (i <= j) ? S[i][j] : 0.0;
+    }
+    lds_upper_inverse(kb, S, Si);
+    __syncthreads();
+    double* wb = work + (long long)b * kB * kB;
+    for (int e = tid; e < kB * kB; e += 256) {
+        const int i = e % kB, j = e / kB;
+        wb[e] = Si[i][j];
+    }
+    if (tid == 0 && s_bad != 0 && info[b] == 0) info[b] = s_bad;
+}
+
+// Invert every 64 x 64 diagonal block of R_b into Rinv_b.
+__global__ __launch_bounds__(256) void trtri_diag_kernel(int n, const double* R, long long ldr, long long sr,
+                                                         double* Rinv, long long ldi, long long si) {
+    __shared__ double S[kB][kB + 1];
+    __shared__ double Si[kB][kB + 1];
+    const int blk = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+    const int o = blk * kB, kb = min(kB, n - o);
+    const double* Rb = R + b * sr + o + (long long)o * ldr;
+    double* Ib = Rinv + b * si + o + (long long)o * ldi;
+    for (int e = tid; e < kB * kB; e += 256) {
+        const int i = e % kB, j = e / kB;
+        S[i][j] = (i < kb && j < kb && i <= j) ? Rb[i + (long long)j * ldr] : (i == j ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    lds_upper_inverse(kb, S, Si);
+    __syncthreads();
+    for (int e = tid; e < kb * kb; e += 256) {
+        const int i = e % kb, j = e / kb;
+        Ib[i + (long long)j * ldi] = Si[i][j];
+    }
+}
+
+}  // namespace
+
+hipError_t potrf_batched(int n, double* Z, long long ldz, long long sz, int batch, int* info_dev, double* work,
+                         hipStream_t st) {
+    hipError_t e = hipMemsetAsync(info_dev, 0, sizeof(int) * batch, st);
+    if (e != hipSuccess) return e;
+    for (int k0 = 0; k0 < n; k0 += kB) {
+        const int kb = n - k0 < kB ? n - k0 : kB;
+        potrf_diag_kernel<<<batch, 256, 0, st>>>(k0, kb, Z, ldz, sz, info_dev, work);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const int rest = n - k0 - kb;
+        if (rest <= 0) break;
+        double* Z12 = Z + k0 + (long long)(k0 + kb) * ldz;
+        // R12 = R_kk^{-T} Z12, in place (one tile row covers all kb rows).
+        GemmDesc g;
+        g.m = kb; g.n = rest; g.k = kb; g.transa = 1; g.transb = 0;
+        g.A = work; g.lda = kB; g.strideA = (long long)kB * kB;
+        g.B = Z12; g.ldb = ldz; g.strideB = sz;
+        g.C = Z12; g.ldc = ldz; g.strideC = sz;
+        g.beta = 0.0; g.batch = batch; g.flags = kALower;
+        if ((e = gemm(g, st)) != hipSuccess) return e;
+        // Z22 -= R12^T R12 on the upper tiles.
+        double* Z22 = Z + (k0 + kb) + (long long)(k0 + kb) * ldz;
+        GemmDesc s;
+        s.m = rest; s.n = rest; s.k = kb; s.transa = 1; s.transb = 0;
+        s.A = Z12; s.lda = ldz; s.strideA = sz;
+        s.B = Z12; s.ldb = ldz; s.strideB = sz;
+        s.Cin = Z22; s.ldcin = ldz; s.strideCin = sz;
+        s.C = Z22; s.ldc = ldz; s.strideC = sz;
+        s.alpha = -1.0; s.beta = 1.0; s.batch = batch;
+        s.flags = kCUpperTiles | kCStoreUpper;
+        if ((e = gemm(s, st)) != hipSuccess) return e;
+    }
+    return zero_strict_lower(n, Z, ldz, sz, batch, st);
+}
+
+hipError_t trtri_batched(int n, const double* R, long long ldr, long long sr, double* Rinv, long long ldi,
+                         long long si, int batch, double* work, long long work_elems, hipStream_t st) {
+    hipError_t e = fill_matrix(n, n, Rinv, ldi, si, batch, 0.0, 0.0, st);
+    if (e != hipSuccess) return e;
+    const int nblk = (n + kB - 1) / kB;
+    trtri_diag_kernel<<<dim3(nblk, batch), 256, 0, st>>>(n, R, ldr, sr, Rinv, ldi, si);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    for (long long s = kB; s < n; s *= 2) {
+        const long long full = n / (2 * s);           // pairs with both blocks of size s
+        const long long o_rag = full * 2 * s;          // a ragged pair starts here if o_rag + s < n
+        const long long s2_rag = n - o_rag - s;
+        const long long per_b = full * s * s + (s2_rag > 0 ? s * s2_rag : 0);
+        if (per_b * batch > work_elems) return hipErrorInvalidValue;
+        for (int part = 0; part < 2; ++part) {
+            const long long npairs = part == 0 ? full : (s2_rag > 0 ? 1 : 0);
+            if (npairs == 0) continue;
+            const long long o = part == 0 ? 0 : o_rag;
+            const long long s2 = part == 0 ? s : s2_rag;
+            double* Wp = work + (part == 0 ? 0 : full * s * s);
+            // W = R12 * R22^{-1}
+            GemmDesc g;
+            g.m = (int)s; g.n = (int)s2; g.k = (int)s2;
+            g.A = R + o + (o + s) * ldr; g.lda = ldr; g.strideA = 2 * s * (ldr + 1);
+            g.B = Rinv + (o + s) + (o + s) * ldi; g.ldb = ldi; g.strideB = 2 * s * (ldi + 1);
+            g.C = Wp; g.ldc = s; g.strideC = s * s2;
+            g.batch = (int)npairs; g.flags = kBUpper;
+            g.batch2 = batch; g.strideA2 = sr; g.strideB2 = si; g.strideC2 = per_b;
+            if ((e = gemm(g, st)) != hipSuccess) return e;
+            // Rinv12 = -R11^{-1} W
+            GemmDesc h;
+            h.m = (int)s; h.n = (int)s2; h.k = (int)s;
+            h.A = Rinv + o + o * ldi; h.lda = ldi; h.strideA = 2 * s * (ldi + 1);
+            h.B = Wp; h.ldb = s; h.strideB = s * s2;
+            h.C = Rinv + o + (o + s) * ldi; h.ldc = ldi; h.strideC = 2 * s * (ldi + 1);
+            h.alpha = -1.0; h.batch = (int)npairs; h.flags = kAUpper;
+            h.batch2 = batch; h.strideA2 = si; h.strideB2 = per_b; h.strideC2 = si;
+            if ((e = gemm(h, st)) != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+}  // namespace zolo

@@ -1,0 +1,200 @@
+// FP64 GEMM on CDNA4 matrix cores (v_mfma_f64_16x16x4f64).
+//
+// Every BLAS3 phase of Zolo-PD (trailing updates and Q formation of the
+// structured QR, the Gram matrix X^T X, the Cholesky trailing updates,
+// triangular inverses, the Zolotarev combination and H = Qp^T A) is a call of
+// this kernel with different structure flags.
+//
+// Tiling: a 256-thread workgroup (4 waves, 2 x 2) owns a BM x BN tile of the
+// result; each wave owns (BM/2) x (BN/2) as a grid of 16 x 16 MFMA blocks held
+// in accumulator registers.  K is walked in BK = 16 slices staged through LDS
+// (k-major, so that a fragment load is 16 consecutive doubles); the next slice
+// is fetched into registers while the current one feeds the MFMAs.  Tiles are
+// ordered in groups of 8 tile-rows and the workgroup ids are remapped so that
+// neighbouring tiles run on the same XCD and reuse its L2.
+#include "common.hpp"
+
+namespace zolo {
+namespace {
+
+constexpr int kBK = 16;
+constexpr int kPad = 4;
+
+// 128 x 128 tiles hold 128 accumulator doubles per lane: one wave per SIMD
+// (512 registers); smaller tiles run two.
+template <int BM, int BN, bool TA, bool TB>
+__global__ __launch_bounds__(256, (BM * BN >= 128 * 128) ? 1 : 2) void dgemm_kernel(GemmDesc d) {
+    constexpr int BK = kBK;
+    constexpr int FM = BM / 32, FN = BN / 32;
+    constexpr int APT = BM * BK / 256, BPT = BN * BK / 256;
+    __shared__ double As[BK][BM + kPad];
+    __shared__ double Bs[BK][BN + kPad];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave & 1) * (BM / 2), wn = (wave >> 1) * (BN / 2);
+    const int tiles_m = (d.m + BM - 1) / BM, tiles_n = (d.n + BN - 1) / BN;
+    const int nblocks = tiles_m * tiles_n;
+    const int lin = xcd_remap(blockIdx.x, nblocks);
+    constexpr int GROUP = 8;
+    const int in_group = GROUP * tiles_n;
+    const int first_m = (lin / in_group) * GROUP;
+    const int gsize = min(tiles_m - first_m, GROUP);
+    const int tm = first_m + (lin % in_group) % gsize;
+    const int tn = (lin % in_group) / gsize;
+    const int row0 = tm * BM, col0 = tn * BN;
+    if ((d.flags & kCUpperTiles) && row0 > col0 + BN - 1) return;
+
+    const unsigned fl = d.flags;
+    int kb = 0, ke = d.k;
+    if (fl & kAUpper) kb = max(kb, row0);
+    if (fl & kBLower) kb = max(kb, col0);
+    if (fl & kALower) ke = min(ke, row0 + BM);
+    if (fl & kBUpper) ke = min(ke, col0 + BN);
+
+    d4 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+    const int nbatch = d.reduce ? d.batch : 1;
+    const int bfirst = d.reduce ? 0 : blockIdx.y;
+    double ra[APT], rb[BPT];
+
+    for (int bi = 0; bi < nbatch; ++bi) {
+        const int b = bfirst + bi;
+        const double* __restrict__ A = d.A + (long long)b * d.strideA + (long long)blockIdx.z * d.strideA2;
+        const double* __restrict__ B = d.B + (long long)b * d.strideB + (long long)blockIdx.z * d.strideB2;
+        const double al = d.nalpha > 0 ? d.alphas[b] : 1.0;
+
+        auto gload = [&](int k0) {
+#pragma unroll
+            for (int s = 0; s < APT; ++s) {
+                const int e = tid + 256 * s;
+                const int i = TA ? e / BK : e % BM;
+                const int kk = TA ? e % BK : e / BM;
+                const int gi = row0 + i, gk = k0 + kk;
+                bool ok = gi < d.m && gk < ke;
+                if (fl & kAUpper) ok = ok && gk >= gi;
+                if (fl & kALower) ok = ok && gk <= gi;
+                double v = 0.0;
+                if (ok) v = TA ? A[gk + (long long)gi * d.lda] : A[gi + (long long)gk * d.lda];
+                ra[s] = v * al;
+            }
+#pragma unroll
+            for (int s = 0; s < BPT; ++s) {
+                const int e = tid + 256 * s;
+                const int j = TB ? e % BN : e / BK;
+                const int kk = TB ? e / BN : e % BK;
+                const int gj = col0 + j, gk = k0 + kk;
+                bool ok = gj < d.n && gk < ke;
+                if (fl & kBUpper) ok = ok && gk <= gj;
+                if (fl & kBLower) ok = ok && gk >= gj;
+                double v = 0.0;
+                if (ok) v = TB ? B[gj + (long long)gk * d.ldb] : B[gk + (long long)gj * d.ldb];
+                rb[s] = v;
+            }
+        };
+        auto lstore = [&]() {
+#pragma unroll
+            for (int s = 0; s < APT; ++s) {
+                const int e = tid + 256 * s;
+                const int i = TA ? e / BK : e % BM;
+                const int kk = TA ? e % BK : e / BM;
+                As[kk][i] = ra[s];
+            }
+#pragma unroll
+            for (int s = 0; s < BPT; ++s) {
+                const int e = tid + 256 * s;
+                const int j = TB ? e % BN : e / BK;
+                const int kk = TB ? e / BN : e % BK;
+                Bs[kk][j] = rb[s];
+            }
+        };
+
+        if (kb >= ke) continue;
+        gload(kb);
+        for (int k0 = kb; k0 < ke; k0 += BK) {
+            __syncthreads();
+            lstore();
+            __syncthreads();
+            if (k0 + BK < ke) gload(k0 + BK);
+#pragma unroll
+            for (int k4 = 0; k4 < BK; k4 += 4) {
+                double af[FM], bf[FN];
+                const int kr = k4 + (lane >> 4);
+#pragma unroll
+                for (int i = 0; i < FM; ++i) af[i] = As[kr][wm + i * 16 + (lane & 15)];
+#pragma unroll
+                for (int j = 0; j < FN; ++j) bf[j] = Bs[kr][wn + j * 16 + (lane & 15)];
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) acc[i][j] = mfma_f64_16x16x4(af[i], bf[j], acc[i][j]);
+            }
+        }
+    }
+
+    const int ob = d.reduce ? 0 : blockIdx.y;
+    double* __restrict__ C = d.C + (long long)ob * d.strideC + (long long)blockIdx.z * d.strideC2;
+    const double* Cin = d.Cin ? d.Cin + (long long)ob * d.strideCin + (long long)blockIdx.z * d.strideCin2 : nullptr;
+    const bool use_cin = Cin != nullptr && d.beta != 0.0;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int gi = row0 + wm + i * 16 + (lane >> 4) * 4 + e;
+                const int gj = col0 + wn + j * 16 + (lane & 15);
+                bool ok = gi < d.m && gj < d.n;
+                if (fl & kCStoreUpper) ok = ok && gi <= gj;
+                if (fl & kCStoreLower) ok = ok && gi >= gj;
+                if (ok) {
+                    double v = d.alpha * acc[i][j][e];
+                    if (use_cin) v += d.beta * Cin[gi + (long long)gj * d.ldcin];
+                    C[gi + (long long)gj * d.ldc] = v;
+                }
+            }
+}
+
+template <int BM, int BN>
+hipError_t launch_bm_bn(const GemmDesc& d, hipStream_t s) {
+    const int tiles = ((d.m + BM - 1) / BM) * ((d.n + BN - 1) / BN);
+    dim3 grid(tiles, d.reduce ? 1 : d.batch, d.batch2);
+    if (!d.transa && !d.transb) dgemm_kernel<BM, BN, false, false><<<grid, 256, 0, s>>>(d);
+    else if (!d.transa && d.transb) dgemm_kernel<BM, BN, false, true><<<grid, 256, 0, s>>>(d);
+    else if (d.transa && !d.transb) dgemm_kernel<BM, BN, true, false><<<grid, 256, 0, s>>>(d);
+    else dgemm_kernel<BM, BN, true, true><<<grid, 256, 0, s>>>(d);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t gemm(const GemmDesc& d, hipStream_t s) {
+    if (d.m <= 0 || d.n <= 0) return hipSuccess;
+    if (d.batch <= 0 || d.batch2 <= 0) return hipSuccess;
+    if (d.nalpha > kMaxInlineAlpha || (d.nalpha > 0 && d.nalpha < d.batch)) return hipErrorInvalidValue;
+    // Small outputs use 64-wide tiles so that the grid still covers the chip.
+    const long long big_tiles =
+        (long long)((d.m + 127) / 128) * ((d.n + 127) / 128) * (d.reduce ? 1 : d.batch) * d.batch2;
+    const bool small_m = d.m <= 64 || big_tiles < 256;
+    const bool small_n = d.n <= 64 || big_tiles < 256;
+    if (small_m && small_n) return launch_bm_bn<64, 64>(d, s);
+    if (small_m) return launch_bm_bn<64, 128>(d, s);
+    if (small_n) return launch_bm_bn<128, 64>(d, s);
+    return launch_bm_bn<128, 128>(d, s);
+}
+
+double gemm_flops(const GemmDesc& d) {
+    double f = 2.0 * d.m * (double)d.n * d.k * d.batch * d.batch2;
+    int tri = 0;
+    if (d.flags & (kAUpper | kALower)) ++tri;
+    if (d.flags & (kBUpper | kBLower)) ++tri;
+    if (tri == 1) f *= 0.5;
+    if (tri == 2) f /= 3.0;
+    if (d.flags & kCUpperTiles) f *= 0.5;
+    return f;
+}
+
+}  // namespace zolo

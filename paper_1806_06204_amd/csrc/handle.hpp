@@ -1,0 +1,16 @@
+// Library handle: stream, device, pinned read-back buffer and the device
+// workspace arena shared by every call made with the handle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+struct zolo_handle_s {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
+    double* host = nullptr;  // pinned scalars for read-back
+    int panel_coresident = 0;
+};

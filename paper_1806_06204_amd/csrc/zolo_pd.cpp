@@ -1,0 +1,485 @@
+// Zolo-PD driver and C ABI (Algorithm 1 of the paper, Algorithm 3 steps 1-4
+// on one GPU).  Every matrix operation is a kernel of this library; the host
+// only computes the per-iteration scalars (coefficients, step kind, stop test)
+// and reads one or two scalars back per iteration.
+//
+// Per iteration, with c, a, Mhat for the current l:
+//   QR-type step (eq. (12)): Y_j = X, D_j = 0 for j = 1..r; one batched
+//     structured QR of [sqrt(c_{2j-1}) I; Y_j] and its explicit Q; then
+//     X <- Mhat X + sum_j (Mhat a_j / sqrt(c_{2j-1})) Q_{j,Y} Q_{j,D}^T as one
+//     batch-reduced GEMM (Q_{j,D} is upper triangular, so the product is a TRMM).
+//   Cholesky-type step (eq. (11), the factors of Algorithm 1 step 4(d)):
+//     G = X^T X; Z_j = G + c_{2j-1} I = R_j^T R_j (batched POTRF);
+//     F = I + sum_j a_j R_j^{-1} R_j^{-T} (batched TRTRI, then one
+//     batch-reduced triangular GEMM); X <- Mhat X F.
+//     Since X (X^T X + c I)^{-1} = X R^{-1} R^{-T}, this is the same matrix
+//     as Mhat (X + sum_j a_j (X R_j^{-1}) R_j^{-T}); summing the n x n
+//     inverses first replaces 2r triangular solves on m x n by one GEMM.
+//   The Cholesky-type step is taken once (1 + c_1)/(l^2 + c_1) <= chol_switch,
+//   i.e. every Z_j has condition number at most chol_switch; a non-positive
+//   pivot redoes the step as QR-type.
+// Stop rules: verified (default) or the paper's relative-change test.
+// Finally H = (Qp^T A + (Qp^T A)^T) / 2.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/zolo.h"
+#include "../../include/zolo_blocks.h"
+#include "coeffs.hpp"
+#include "handle.hpp"
+#include "misc.hpp"
+
+namespace zolo {
+int panel_max_coresident();
+}
+
+using namespace zolo;
+
+
+namespace {
+
+constexpr double kEps = 2.220446049250313e-16;
+
+struct Arena {
+    char* base;
+    size_t off = 0;
+    template <class T>
+    T* take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T* p = reinterpret_cast<T*>(base + off);
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+struct Work {
+    double *X, *Xn, *Y, *D, *G, *F, *trtri, *potrf, *part, *scal, *vec_v, *vec_u, *vec_w, *lam;
+    int* iflags;  // [0] nonfinite, [1] panel error, [2..] potrf info per j
+    QrWork qr;
+    size_t bytes;
+};
+
+// Lay out (or size, if base == nullptr) the workspace for m x n and degree rmax.
+Work layout(char* base, int m, int n, int rmax, int panel_coresident) {
+    Arena ar{base};
+    const size_t mn = (size_t)m * n, nn = (size_t)n * n;
+    const int npanels = (n + kPanelNB - 1) / kPanelNB;
+    const int maxG = std::max(1, std::min((m + 63) / 64, std::max(1, panel_coresident)));
+    Work w{};
+    w.X = ar.take<double>(mn);
+    w.Xn = ar.take<double>(mn);
+    w.Y = ar.take<double>(mn * rmax);
+    w.D = ar.take<double>(nn * rmax);
+    w.G = ar.take<double>(nn);
+    w.F = ar.take<double>(nn);
+    w.trtri = ar.take<double>(nn * rmax / 2 + (size_t)64 * 64 * rmax + 64);
+    w.potrf = ar.take<double>((size_t)64 * 64 * rmax);
+    w.part = ar.take<double>(4096);
+    w.scal = ar.take<double>(64);
+    w.vec_v = ar.take<double>(n);
+    w.vec_u = ar.take<double>(m);
+    w.vec_w = ar.take<double>(n);
+    w.lam = ar.take<double>(128);
+    w.iflags = ar.take<int>(64);
+    w.qr.W = ar.take<double>((size_t)rmax * kPanelNB * n);
+    w.qr.T = ar.take<double>((size_t)rmax * npanels * kPanelNB * kPanelNB);
+    w.qr.partials = ar.take<double>((size_t)rmax * 2 * maxG * kPanelNB);
+    w.qr.counters = ar.take<unsigned>((size_t)rmax * npanels);
+    w.qr.error_flag = w.iflags + 1;
+    w.qr.max_coresident = panel_coresident;
+    w.bytes = ar.off + 256;
+    return w;
+}
+
+int ensure(zolo_handle h, size_t bytes) {
+    if (h->arena_bytes >= bytes) return 0;
+    if (h->arena) {
+        (void)hipStreamSynchronize(h->stream);
+        (void)hipFree(h->arena);
+        h->arena = nullptr;
+        h->arena_bytes = 0;
+    }
+    if (hipMalloc(&h->arena, bytes) != hipSuccess) {
+        h->arena = nullptr;
+        return ZOLO_ALLOC;
+    }
+    h->arena_bytes = bytes;
+    return 0;
+}
+
+struct Timer {
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    double lap() {
+        auto t = std::chrono::steady_clock::now();
+        double ms = std::chrono::duration<double, std::milli>(t - t0).count();
+        t0 = t;
+        return ms;
+    }
+};
+
+#define HIPCHECK(x)                                  \
+    do {                                             \
+        if ((x) != hipSuccess) return ZOLO_HIP;      \
+    } while (0)
+
+int readback(zolo_handle h, const void* dev, size_t bytes) {
+    HIPCHECK(hipMemcpyAsync(h->host, dev, bytes, hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    return 0;
+}
+
+// G = X^T X (upper tiles; symmetric result in the upper triangle).
+hipError_t gram(int m, int n, const double* X, long long ldx, double* G, hipStream_t st) {
+    GemmDesc g;
+    g.m = n; g.n = n; g.k = m; g.transa = 1;
+    g.A = X; g.lda = ldx; g.B = X; g.ldb = ldx;
+    g.C = G; g.ldc = n;
+    g.flags = kCUpperTiles | kCStoreUpper;
+    return gemm(g, st);
+}
+
+struct StepCtx {
+    zolo_handle h;
+    const Work* w;
+    int m, n;
+    double flops_exec = 0.0;
+};
+
+// One Cholesky-type step X -> Xn.  Returns 0, ZOLO_BREAKDOWN, or an error.
+int chol_step(StepCtx& cx, const Coeffs& co, bool g_valid) {
+    const Work& w = *cx.w;
+    const int m = cx.m, n = cx.n, r = co.r;
+    hipStream_t st = cx.h->stream;
+    const long long nn = (long long)n * n;
+    if (!g_valid) {
+        HIPCHECK(gram(m, n, w.X, m, w.G, st));
+        cx.flops_exec += (double)m * n * n;
+    }
+    ShiftArgs sh;
+    sh.batch = r;
+    for (int j = 0; j < r; ++j) sh.shift[j] = co.c[2 * j];
+    HIPCHECK(shift_copy(n, w.G, n, w.Y, n, nn, sh, st));
+    HIPCHECK(potrf_batched(n, w.Y, n, nn, r, w.iflags + 2, w.potrf, st));
+    int rc = readback(cx.h, w.iflags + 2, sizeof(int) * r);
+    if (rc) return rc;
+    for (int j = 0; j < r; ++j)
+        if (reinterpret_cast<int*>(cx.h->host)[j] != 0) return ZOLO_BREAKDOWN;
+    HIPCHECK(trtri_batched(n, w.Y, n, nn, w.D, n, nn, r, w.trtri, (long long)nn * r / 2 + 64 * 64 * r, st));
+    // F = sum_j a_j R_j^{-1} R_j^{-T} (upper tiles), then mirror and add I.
+    GemmDesc f;
+    f.m = n; f.n = n; f.k = n; f.transb = 1;
+    f.A = w.D; f.lda = n; f.strideA = nn;
+    f.B = w.D; f.ldb = n; f.strideB = nn;
+    f.C = w.G; f.ldc = n;
+    f.batch = r; f.reduce = 1; f.nalpha = r;
+    for (int j = 0; j < r; ++j) f.alphas[j] = co.a[j];
+    f.flags = kAUpper | kBLower | kCUpperTiles | kCStoreUpper;
+    HIPCHECK(gemm(f, st));
+    HIPCHECK(symmetrize(n, w.G, n, w.F, n, 1, 1.0, st));
+    GemmDesc x;
+    x.m = m; x.n = n; x.k = n;
+    x.A = w.X; x.lda = m; x.B = w.F; x.ldb = n;
+    x.C = w.Xn; x.ldc = m; x.alpha = co.mhat;
+    HIPCHECK(gemm(x, st));
+    cx.flops_exec += r * (double)n * n * n + 2.0 * m * (double)n * n;
+    return 0;
+}
+
+int qr_step(StepCtx& cx, const Coeffs& co) {
+    const Work& w = *cx.w;
+    const int m = cx.m, n = cx.n, r = co.r;
+    hipStream_t st = cx.h->stream;
+    const long long mn = (long long)m * n, nn = (long long)n * n;
+    HIPCHECK(broadcast_copy(m, n, w.X, m, w.Y, m, mn, r, st));
+    HIPCHECK(hipMemsetAsync(w.D, 0, sizeof(double) * nn * r, st));
+    double piv[kMaxInlineAlpha];
+    for (int j = 0; j < r; ++j) piv[j] = std::sqrt(co.c[2 * j]);
+    HIPCHECK(structured_geqrf(m, n, w.Y, m, mn, w.D, n, nn, piv, r, w.qr, st));
+    HIPCHECK(structured_orgqr(m, n, w.Y, m, mn, w.D, n, nn, r, w.qr, st));
+    GemmDesc g;
+    g.m = m; g.n = n; g.k = n; g.transb = 1;
+    g.A = w.Y; g.lda = m; g.strideA = mn;
+    g.B = w.D; g.ldb = n; g.strideB = nn;
+    g.Cin = w.X; g.ldcin = m; g.beta = co.mhat;
+    g.C = w.Xn; g.ldc = m;
+    g.alpha = co.mhat; g.batch = r; g.reduce = 1; g.nalpha = r;
+    for (int j = 0; j < r; ++j) g.alphas[j] = co.a[j] / piv[j];
+    g.flags = kBLower;
+    HIPCHECK(gemm(g, st));
+    cx.flops_exec += 5.0 * r * m * (double)n * n;
+    return 0;
+}
+
+bool opts_ok(const zolo_opts& o) {
+    return o.max_iter >= 1 && o.max_iter <= ZOLO_MAX_ITER && (o.stop_rule == 0 || o.stop_rule == 1) &&
+           o.tau > 0.0 && o.chol_switch >= 1.0 && (o.qr_variant == 0 || o.qr_variant == 1) && o.precision == 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+void zolo_default_opts(zolo_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->max_iter = 10;
+    o->stop_rule = 0;
+    o->tau = 5e-14;
+    o->chol_switch = 100.0;
+    o->qr_variant = 0;
+    o->precision = 0;
+    o->compute_errors = 0;
+}
+
+int zolo_create(zolo_handle* out, void* stream) {
+    if (!out) return -1;
+    *out = nullptr;
+    zolo_handle h = new (std::nothrow) zolo_handle_s();
+    if (!h) return ZOLO_ALLOC;
+    h->stream = (hipStream_t)stream;
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return ZOLO_HIP;
+    }
+    if (hipHostMalloc((void**)&h->host, 4096) != hipSuccess) {
+        delete h;
+        return ZOLO_HIP;
+    }
+    h->panel_coresident = panel_max_coresident();
+    if (h->panel_coresident <= 0) {
+        (void)hipHostFree(h->host);
+        delete h;
+        return ZOLO_HIP;
+    }
+    *out = h;
+    return 0;
+}
+
+int zolo_set_stream(zolo_handle h, void* stream) {
+    if (!h) return -1;
+    h->stream = (hipStream_t)stream;
+    return 0;
+}
+
+int zolo_destroy(zolo_handle h) {
+    if (!h) return -1;
+    if (h->arena) {
+        (void)hipStreamSynchronize(h->stream);
+        (void)hipFree(h->arena);
+    }
+    if (h->host) (void)hipHostFree(h->host);
+    delete h;
+    return 0;
+}
+
+int zolo_coeffs(double l, int r, double* c, double* a, double* mhat, double* l_next) {
+    Coeffs co;
+    const int rc = compute_coeffs(l, r, &co);
+    if (rc) return rc;
+    if (c)
+        for (int i = 0; i < 2 * r; ++i) c[i] = co.c[i];
+    if (a)
+        for (int j = 0; j < r; ++j) a[j] = co.a[j];
+    if (mhat) *mhat = co.mhat;
+    if (l_next) *l_next = co.l_next;
+    return 0;
+}
+
+int zolo_pd(zolo_handle h, int m, int n, const double* A, int lda, double alpha, double l, int r, double* Qp,
+            int ldq, double* H, int ldh, const zolo_opts* opts_in, zolo_info* info) {
+    if (!h) return -1;
+    if (m < 1) return -2;
+    if (n < 1 || n > m) return -3;
+    if (!A) return -4;
+    if (lda < m) return -5;
+    if (std::isnan(alpha)) return -6;
+    if (std::isnan(l) || l > 1.0) return -7;
+    if (r > kMaxR) return -8;
+    if (!Qp) return -9;
+    if (ldq < m) return -10;
+    if (!H) return -11;
+    if (ldh < n) return -12;
+    zolo_opts opts;
+    zolo_default_opts(&opts);
+    if (opts_in) opts = *opts_in;
+    if (!opts_ok(opts)) return -13;
+
+    zolo_info inf;
+    std::memset(&inf, 0, sizeof(inf));
+    inf.orth_check = -1.0;
+    inf.bwd_err = -1.0;
+    inf.orth_err = -1.0;
+    Timer whole, stage;
+    const int rmax = r >= 1 ? r : kMaxR;
+    Work w = layout(nullptr, m, n, rmax, h->panel_coresident);
+    int rc = ensure(h, w.bytes);
+    if (rc) {
+        inf.status = rc;
+        if (info) *info = inf;
+        return rc;
+    }
+    w = layout(h->arena, m, n, rmax, h->panel_coresident);
+    hipStream_t st = h->stream;
+    const long long mn = (long long)m * n;
+    int* hi = reinterpret_cast<int*>(h->host);
+    auto finish = [&](int status) {
+        inf.status = status;
+        inf.t_stage[7] = whole.lap();
+        if (info) *info = inf;
+        return status;
+    };
+
+    HIPCHECK(hipMemsetAsync(w.iflags, 0, sizeof(int) * 64, st));
+    // Step 1: alpha (upper bound of sigma_max) and X0 = A / alpha.
+    if (!(alpha > 0.0)) {
+        HIPCHECK(fill_vector(n, w.vec_v, 1.0 / std::sqrt((double)n), st));
+        double lam_prev = 0.0, lam = 0.0;
+        bool done = false;
+        for (int chunk = 0; chunk < 10 && !done; ++chunk) {
+            for (int it = 0; it < 10; ++it)
+                HIPCHECK(power_step(m, n, A, lda, w.vec_v, w.vec_u, w.vec_w, w.lam + it, st));
+            if ((rc = readback(h, w.lam, sizeof(double) * 10))) return finish(rc);
+            for (int it = 0; it < 10; ++it) {
+                lam = h->host[it];
+                if ((chunk > 0 || it > 0) && std::fabs(lam - lam_prev) <= 1e-10 * lam) done = true;
+                lam_prev = lam;
+            }
+        }
+        inf.flops_exec += 4.0 * m * (double)n * 100;
+        alpha = 1.01 * std::sqrt(std::max(lam, 0.0));
+        if (!(alpha > 0.0)) return finish(-6);
+    }
+    inf.alpha = alpha;
+    HIPCHECK(scale_copy(m, n, A, lda, w.X, m, 1.0 / alpha, w.iflags, st));
+    if ((rc = readback(h, w.iflags, sizeof(int)))) return finish(rc);
+    if (hi[0]) return finish(ZOLO_NONFINITE);
+
+    // Step 2: l, a lower bound on sigma_min(X0).
+    if (!(l > 0.0)) {
+        // X0 = Q R via the structured QR with a zero identity block, then
+        // l = 1 / (sqrt(n) ||R^{-1}||_1) <= 1 / ||R^{-1}||_2 = sigma_min(X0).
+        HIPCHECK(hipMemcpyAsync(w.Y, w.X, sizeof(double) * mn, hipMemcpyDeviceToDevice, st));
+        HIPCHECK(hipMemsetAsync(w.D, 0, sizeof(double) * n * (size_t)n, st));
+        double zero = 0.0;
+        HIPCHECK(structured_geqrf(m, n, w.Y, m, mn, w.D, n, (long long)n * n, &zero, 1, w.qr, st));
+        HIPCHECK(trtri_batched(n, w.D, n, (long long)n * n, w.G, n, (long long)n * n, 1, w.trtri,
+                               (long long)n * n / 2 + 64 * 64, st));
+        HIPCHECK(norm1_upper(n, w.G, n, w.vec_u, w.scal, st));
+        if ((rc = readback(h, w.scal, sizeof(double)))) return finish(rc);
+        const double nrm = h->host[0];
+        l = (std::isfinite(nrm) && nrm > 0.0) ? 1.0 / (std::sqrt((double)n) * nrm) : kLMin;
+        inf.flops_exec += 2.0 * m * (double)n * n + (double)n * n * n / 3.0;
+    }
+    if (l < kLMin) l = kLMin;
+    if (l > 1.0) l = 1.0;
+    inf.l0 = l;
+    // Step 3: r.
+    if (r < 1) r = choose_r(l);
+    inf.r_used = r;
+    inf.t_stage[0] += stage.lap();
+
+    StepCtx cx{h, &w, m, n};
+    bool g_valid = false;   // G holds X^T X of the current X
+    int status = ZOLO_NOT_CONVERGED;
+    Coeffs co;
+    for (int it = 0; it < opts.max_iter; ++it) {
+        compute_coeffs(l, r, &co);
+        inf.l_seq[it] = l;
+        char kind = co.kappa_z > opts.chol_switch ? 'Q' : 'C';
+        if (kind == 'C') {
+            rc = chol_step(cx, co, g_valid);
+            if (rc == ZOLO_BREAKDOWN) {
+                ++inf.chol_fallbacks;
+                kind = 'Q';
+            } else if (rc) {
+                return finish(rc);
+            }
+            inf.t_stage[2] += stage.lap();
+        }
+        if (kind == 'Q') {
+            if ((rc = qr_step(cx, co))) return finish(rc);
+            if ((rc = readback(h, w.iflags + 1, sizeof(int)))) return finish(rc);
+            if (hi[0]) return finish(ZOLO_KERNEL);
+            inf.t_stage[1] += stage.lap();
+        }
+        g_valid = false;
+        inf.kind[it] = kind;
+        inf.iters = it + 1;
+        inf.flops_paper += kind == 'Q' ? 5.0 * r * m * (double)n * n
+                                       : m * (double)n * n + r * ((double)n * n * n / 3.0 + 2.0 * m * (double)n * n);
+        const double l_pred = co.l_next;
+        if (opts.stop_rule == 1) {
+            HIPCHECK(frob2(m, n, w.Xn, m, w.X, m, w.part, w.scal, st));
+            std::swap(w.X, w.Xn);
+            if ((rc = readback(h, w.scal, 2 * sizeof(double)))) return finish(rc);
+            const double rel = std::sqrt(h->host[0]) / std::sqrt(h->host[1]);
+            l = l_pred;
+            inf.t_stage[3] += stage.lap();
+            if (rel <= std::pow(kEps, 1.0 / (2 * r + 1))) {
+                status = 0;
+                break;
+            }
+        } else {
+            std::swap(w.X, w.Xn);
+            if (l_pred >= kConverged) {
+                HIPCHECK(gram(m, n, w.X, m, w.G, st));
+                HIPCHECK(orth2(n, w.G, n, w.part, w.scal, st));
+                if ((rc = readback(h, w.scal, sizeof(double)))) return finish(rc);
+                cx.flops_exec += (double)m * n * n;
+                inf.flops_paper += (double)m * n * n;
+                g_valid = true;
+                const double d = std::sqrt(std::max(h->host[0], 0.0)) / std::sqrt((double)n);
+                inf.orth_check = d;
+                inf.t_stage[3] += stage.lap();
+                if (d <= opts.tau) {
+                    status = 0;
+                    break;
+                }
+                const double bnd = std::sqrt((double)n) * d;
+                l = bnd < 1.0 ? std::sqrt(std::max(kLMin * kLMin, 1.0 - bnd)) : l_pred / 10.0;
+            } else {
+                l = l_pred;
+            }
+        }
+    }
+    inf.kind[inf.iters] = 0;
+
+    // Step 5: Qp = X, H = (Qp^T A + (Qp^T A)^T) / 2.
+    HIPCHECK(hipMemcpy2DAsync(Qp, sizeof(double) * ldq, w.X, sizeof(double) * m, sizeof(double) * m, n,
+                              hipMemcpyDeviceToDevice, st));
+    GemmDesc hg;
+    hg.m = n; hg.n = n; hg.k = m; hg.transa = 1;
+    hg.A = w.X; hg.lda = m; hg.B = A; hg.ldb = lda;
+    hg.C = w.F; hg.ldc = n;
+    HIPCHECK(gemm(hg, st));
+    HIPCHECK(symmetrize(n, w.F, n, H, ldh, 0, 0.0, st));
+    cx.flops_exec += 2.0 * m * (double)n * n;
+    inf.flops_paper += 2.0 * m * (double)n * n;
+    HIPCHECK(hipStreamSynchronize(st));
+    inf.t_stage[4] += stage.lap();
+
+    if (opts.compute_errors) {
+        GemmDesc pg;  // Xn = Qp H
+        pg.m = m; pg.n = n; pg.k = n;
+        pg.A = Qp; pg.lda = ldq; pg.B = H; pg.ldb = ldh;
+        pg.C = w.Xn; pg.ldc = m;
+        HIPCHECK(gemm(pg, st));
+        HIPCHECK(frob2(m, n, A, lda, w.Xn, m, w.part, w.scal, st));
+        HIPCHECK(gram(m, n, Qp, ldq, w.G, st));
+        HIPCHECK(orth2(n, w.G, n, w.part, w.scal + 2, st));
+        if ((rc = readback(h, w.scal, 3 * sizeof(double)))) return finish(rc);
+        inf.bwd_err = std::sqrt(h->host[0]) / std::sqrt(h->host[1]);
+        inf.orth_err = std::sqrt(std::max(h->host[2], 0.0)) / std::sqrt((double)n);
+    }
+    inf.flops_exec += cx.flops_exec;
+    return finish(status);
+}
+
+}  // extern "C"

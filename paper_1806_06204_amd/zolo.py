@@ -1,0 +1,268 @@
+"""ctypes binding of libzolo.so (include/zolo.h, include/zolo_blocks.h).
+
+Argument marshalling only: every matrix operation runs in the library's HIP
+kernels.  PyTorch supplies device memory and the current HIP stream.
+
+Matrices cross the boundary in column-major order.  A tensor ``A`` of shape
+(m, n) is passed as-is when it is already column-major (``A.stride() ==
+(1, ld)``), otherwise as ``A.t().contiguous()``.  Results come back as
+column-major views (``buf.t()``), which behave like ordinary (m, n) tensors.
+Stacks of matrices for the batched building blocks are tensors of shape
+(batch, m, n) and are handled the same way per matrix.
+"""
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libzolo.so")
+
+c_int, c_double, c_void_p, c_longlong = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_longlong
+MAX_ITER = 16
+STATUS = {0: "ok", 1: "not converged", 2: "non-finite input", 3: "allocation failed", 4: "HIP error",
+          5: "kernel barrier failure", 6: "factorisation breakdown"}
+
+
+class ZoloOpts(ctypes.Structure):
+    _fields_ = [("max_iter", c_int), ("stop_rule", c_int), ("tau", c_double), ("chol_switch", c_double),
+                ("qr_variant", c_int), ("precision", c_int), ("compute_errors", c_int),
+                ("reserved", c_int * 9)]
+
+
+class ZoloInfo(ctypes.Structure):
+    _fields_ = [("status", c_int), ("iters", c_int), ("r_used", c_int), ("chol_fallbacks", c_int),
+                ("kind", ctypes.c_char * (MAX_ITER + 1)), ("alpha", c_double), ("l0", c_double),
+                ("l_seq", c_double * MAX_ITER), ("orth_check", c_double), ("t_stage", c_double * 8),
+                ("flops_exec", c_double), ("flops_paper", c_double), ("bwd_err", c_double),
+                ("orth_err", c_double)]
+
+    def as_dict(self):
+        it = self.iters
+        return {"status": self.status, "iters": it, "r": self.r_used, "chol_fallbacks": self.chol_fallbacks,
+                "kinds": list(self.kind.decode()), "alpha": self.alpha, "l0": self.l0,
+                "ls": list(self.l_seq[:it]), "orth_check": self.orth_check,
+                "t_stage_ms": list(self.t_stage), "flops_exec": self.flops_exec,
+                "flops_paper": self.flops_paper, "bwd_err": self.bwd_err, "orth_err": self.orth_err}
+
+
+_lib = None
+
+EXPORTS = ["zolo_default_opts", "zolo_create", "zolo_set_stream", "zolo_destroy", "zolo_coeffs", "zolo_pd",
+           "zolo_svd", "zolo_dgemm", "zolo_dpotrf_batched", "zolo_dtrtri_batched",
+           "zolo_structured_qr_batched"]
+
+
+def load():
+    """Load libzolo.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(python -m paper_1806_06204_amd.build_lib)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = c_void_p
+    D = ctypes.POINTER(c_double)
+    lib.zolo_default_opts.argtypes = [ctypes.POINTER(ZoloOpts)]
+    lib.zolo_default_opts.restype = None
+    lib.zolo_create.argtypes = [ctypes.POINTER(P), P]
+    lib.zolo_set_stream.argtypes = [P, P]
+    lib.zolo_destroy.argtypes = [P]
+    lib.zolo_coeffs.argtypes = [c_double, c_int, D, D, D, D]
+    lib.zolo_pd.argtypes = [P, c_int, c_int, P, c_int, c_double, c_double, c_int, P, c_int, P, c_int,
+                            ctypes.POINTER(ZoloOpts), ctypes.POINTER(ZoloInfo)]
+    lib.zolo_svd.argtypes = [P, c_int, c_int, P, c_int, c_double, c_double, c_int, P, c_int, D, P, c_int,
+                             ctypes.POINTER(ZoloOpts), ctypes.POINTER(ZoloInfo)]
+    lib.zolo_dgemm.argtypes = [P, c_int, c_int, c_int, c_int, c_int, c_double, P, c_int, c_longlong, P, c_int,
+                               c_longlong, c_double, P, c_int, c_longlong, c_int]
+    lib.zolo_dpotrf_batched.argtypes = [P, c_int, P, c_int, c_longlong, c_int, ctypes.POINTER(c_int)]
+    lib.zolo_dtrtri_batched.argtypes = [P, c_int, P, c_int, c_longlong, P, c_int, c_longlong, c_int]
+    lib.zolo_structured_qr_batched.argtypes = [P, c_int, c_int, D, P, c_int, c_longlong, P, c_int, c_longlong,
+                                               c_int, c_int]
+    for name in EXPORTS:
+        if name not in ("zolo_default_opts",):
+            getattr(lib, name).restype = c_int
+    _lib = lib
+    return lib
+
+
+def coeffs(l, r):
+    """Host-only Zolotarev coefficients: dict(c, a, mhat, l_next)."""
+    lib = load()
+    c = (c_double * (2 * r))()
+    a = (c_double * r)()
+    mh = c_double()
+    ln = c_double()
+    rc = lib.zolo_coeffs(float(l), int(r), c, a, ctypes.byref(mh), ctypes.byref(ln))
+    if rc != 0:
+        raise ValueError(f"zolo_coeffs rejected l={l}, r={r} (code {rc})")
+    return {"c": list(c), "a": list(a), "mhat": mh.value, "l_next": ln.value}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _colmajor(A):
+    """(tensor whose memory is A column-major, leading dimension)."""
+    if A.dim() == 2 and A.stride(0) == 1 and A.stride(1) >= max(1, A.shape[0]):
+        return A, A.stride(1)
+    return A.t().contiguous().t(), A.shape[0]
+
+
+def _check_tensor(A, name):
+    torch = _torch()
+    if not isinstance(A, torch.Tensor) or A.device.type != "cuda" or A.dtype != torch.float64:
+        raise TypeError(f"{name} must be a float64 CUDA/HIP tensor")
+
+
+class ZoloError(RuntimeError):
+    pass
+
+
+def _raise(rc, what):
+    if rc < 0:
+        raise ValueError(f"{what}: argument {-rc} is invalid")
+    raise ZoloError(f"{what}: {STATUS.get(rc, rc)} (code {rc})")
+
+
+class Zolo:
+    """A library handle bound to the current device and a HIP stream."""
+
+    def __init__(self, stream=None):
+        torch = _torch()
+        self.lib = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the Zolo-PD library runs on HIP devices only")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = c_void_p()
+        rc = self.lib.zolo_create(ctypes.byref(h), c_void_p(self.stream.cuda_stream))
+        if rc != 0:
+            _raise(rc, "zolo_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.zolo_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def options(**kw):
+        o = ZoloOpts()
+        load().zolo_default_opts(ctypes.byref(o))
+        names = {"max_iter", "stop_rule", "tau", "chol_switch", "qr_variant", "precision", "compute_errors"}
+        for k, v in kw.items():
+            if k not in names:
+                raise TypeError(f"unknown option {k}")
+            if k == "stop_rule" and isinstance(v, str):
+                v = {"verified": 0, "paper": 1}[v]
+            setattr(o, k, v)
+        return o
+
+    def pd(self, A, alpha=None, l=None, r=None, check=True, **opts):
+        """Polar decomposition A = Qp H.  Returns (Qp, H, info)."""
+        torch = _torch()
+        _check_tensor(A, "A")
+        m, n = A.shape
+        Ac, lda = _colmajor(A)
+        Qbuf = torch.empty((n, m), dtype=torch.float64, device=A.device)
+        Hbuf = torch.empty((n, n), dtype=torch.float64, device=A.device)
+        o = self.options(**opts)
+        info = ZoloInfo()
+        rc = self.lib.zolo_pd(self.h, m, n, c_void_p(Ac.data_ptr()), lda,
+                              float(alpha) if alpha is not None else 0.0,
+                              float(l) if l is not None else 0.0, int(r) if r is not None else 0,
+                              c_void_p(Qbuf.data_ptr()), m, c_void_p(Hbuf.data_ptr()), n,
+                              ctypes.byref(o), ctypes.byref(info))
+        if check and rc not in (0, 1):
+            _raise(rc, "zolo_pd")
+        return Qbuf.t(), Hbuf.t(), info.as_dict()
+
+    def svd(self, A, alpha=None, l=None, r=None, check=True, **opts):
+        """Zolo-SVD A = U diag(S) V^T.  Returns (U, S (numpy), V, info)."""
+        torch = _torch()
+        import numpy as np
+        _check_tensor(A, "A")
+        m, n = A.shape
+        Ac, lda = _colmajor(A)
+        Ubuf = torch.empty((n, m), dtype=torch.float64, device=A.device)
+        Vbuf = torch.empty((n, n), dtype=torch.float64, device=A.device)
+        S = np.zeros(n)
+        o = self.options(**opts)
+        info = ZoloInfo()
+        rc = self.lib.zolo_svd(self.h, m, n, c_void_p(Ac.data_ptr()), lda,
+                               float(alpha) if alpha is not None else 0.0,
+                               float(l) if l is not None else 0.0, int(r) if r is not None else 0,
+                               c_void_p(Ubuf.data_ptr()), m, S.ctypes.data_as(ctypes.POINTER(c_double)),
+                               c_void_p(Vbuf.data_ptr()), n, ctypes.byref(o), ctypes.byref(info))
+        if check and rc not in (0, 1):
+            _raise(rc, "zolo_svd")
+        return Ubuf.t(), S, Vbuf.t(), info.as_dict()
+
+    # -- building blocks ----------------------------------------------------
+    @staticmethod
+    def _stack_cm(X):
+        """(batch, rows, cols) tensor -> contiguous buffer (batch, cols, rows)."""
+        return X.transpose(-1, -2).contiguous()
+
+    def gemm(self, A, B, C=None, transa=False, transb=False, alpha=1.0, beta=0.0):
+        """Batched C = alpha op(A) op(B) + beta C on (batch, rows, cols) stacks."""
+        torch = _torch()
+        Ab, Bb = self._stack_cm(A), self._stack_cm(B)
+        batch = A.shape[0]
+        m = A.shape[2] if transa else A.shape[1]
+        k = A.shape[1] if transa else A.shape[2]
+        n = B.shape[1] if transb else B.shape[2]
+        if C is None:
+            Cb = torch.zeros((batch, n, m), dtype=torch.float64, device=A.device)
+        else:
+            Cb = self._stack_cm(C)
+        rc = self.lib.zolo_dgemm(self.h, int(transa), int(transb), m, n, k, float(alpha),
+                                 c_void_p(Ab.data_ptr()), A.shape[1], A.shape[1] * A.shape[2],
+                                 c_void_p(Bb.data_ptr()), B.shape[1], B.shape[1] * B.shape[2], float(beta),
+                                 c_void_p(Cb.data_ptr()), m, m * n, batch)
+        if rc:
+            _raise(rc, "zolo_dgemm")
+        return Cb.transpose(-1, -2)
+
+    def potrf(self, Z):
+        """Batched upper Cholesky of a (batch, n, n) stack: returns (R, info list)."""
+        Zb = self._stack_cm(Z)
+        batch, n = Z.shape[0], Z.shape[1]
+        info = (c_int * batch)()
+        rc = self.lib.zolo_dpotrf_batched(self.h, n, c_void_p(Zb.data_ptr()), n, n * n, batch, info)
+        if rc not in (0, 6):
+            _raise(rc, "zolo_dpotrf_batched")
+        return Zb.transpose(-1, -2), list(info)
+
+    def trtri(self, R):
+        torch = _torch()
+        Rb = self._stack_cm(R)
+        batch, n = R.shape[0], R.shape[1]
+        Ib = torch.empty_like(Rb)
+        rc = self.lib.zolo_dtrtri_batched(self.h, n, c_void_p(Rb.data_ptr()), n, n * n,
+                                          c_void_p(Ib.data_ptr()), n, n * n, batch)
+        if rc:
+            _raise(rc, "zolo_dtrtri_batched")
+        return Ib.transpose(-1, -2)
+
+    def structured_qr(self, Y, pivots, form_q=True):
+        """QR of [p_b I; Y_b] for a (batch, m, n) stack.  Returns (top, bottom):
+        form_q: (Q_D, Q_Y); else (R, Householder Y-parts)."""
+        torch = _torch()
+        Yb = self._stack_cm(Y)
+        batch, m, n = Y.shape
+        Db = torch.empty((batch, n, n), dtype=torch.float64, device=Y.device)
+        piv = (c_double * batch)(*[float(p) for p in pivots])
+        rc = self.lib.zolo_structured_qr_batched(self.h, m, n, piv, c_void_p(Yb.data_ptr()), m, m * n,
+                                                 c_void_p(Db.data_ptr()), n, n * n, batch, int(form_q))
+        if rc:
+            _raise(rc, "zolo_structured_qr_batched")
+        return Db.transpose(-1, -2), Yb.transpose(-1, -2)

@@ -1,0 +1,121 @@
+"""GPU parity of the library's building blocks (through the C ABI) against
+NumPy FP64 references and the oracle's own factorisations.  Shapes span
+several tiles and ragged tails (64-row MFMA tiles, 64-column panels)."""
+
+import numpy as np
+import pytest
+
+from oracle import dense
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def z():
+    import torch
+    from paper_1806_06204_amd import zolo
+    assert torch.cuda.is_available()
+    h = zolo.Zolo()
+    yield h
+    h.close()
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+@pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
+@pytest.mark.parametrize("m,n,k", [(16, 16, 4), (1, 1, 1), (37, 53, 29), (130, 70, 200), (257, 129, 65)])
+def test_gemm(z, ta, tb, m, n, k):
+    rng = np.random.default_rng(m * 7 + n * 3 + k + 11 * ta + 5 * tb)
+    batch = 2
+    A = rng.standard_normal((batch, k, m) if ta else (batch, m, k))
+    B = rng.standard_normal((batch, n, k) if tb else (batch, k, n))
+    C = rng.standard_normal((batch, m, n))
+    out = z.gemm(dev(A), dev(B), dev(C), transa=ta, transb=tb, alpha=0.7, beta=-1.3).cpu().numpy()
+    opA = np.swapaxes(A, 1, 2) if ta else A
+    opB = np.swapaxes(B, 1, 2) if tb else B
+    ref = 0.7 * opA @ opB - 1.3 * C
+    assert np.abs(out - ref).max() <= 1e-13 * (k + 1) * 4
+
+
+def test_gemm_mfma_layout_identity(z):
+    # Each output element must land in its own (row, column): product with a
+    # permutation-like operand exposes any lane-layout mix-up.
+    rng = np.random.default_rng(1)
+    A = rng.standard_normal((1, 128, 128))
+    P = np.eye(128)[rng.permutation(128)][None]
+    out = z.gemm(dev(A), dev(P)).cpu().numpy()
+    assert np.array_equal(out, A @ P)
+
+
+def test_gemm_large(z):
+    rng = np.random.default_rng(2)
+    A = rng.standard_normal((1, 1000, 777))
+    B = rng.standard_normal((1, 777, 1031))
+    out = z.gemm(dev(A), dev(B)).cpu().numpy()
+    assert np.abs(out - A @ B).max() <= 1e-12 * 777
+
+
+@pytest.mark.parametrize("n", [1, 64, 200])
+def test_potrf(z, n):
+    rng = np.random.default_rng(n)
+    Zs = []
+    for b in range(3):
+        M = rng.standard_normal((n + 10, n))
+        Zs.append(M.T @ M + 0.5 * np.eye(n))
+    Zs = np.stack(Zs)
+    R, info = z.potrf(dev(Zs))
+    R = R.cpu().numpy()
+    assert info == [0, 0, 0]
+    for b in range(3):
+        ref = dense.cholesky_upper(Zs[b])
+        assert np.allclose(np.tril(R[b], -1), 0.0)
+        assert np.abs(R[b] - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_potrf_breakdown_reported(z):
+    n = 150
+    rng = np.random.default_rng(9)
+    M = rng.standard_normal((n, n))
+    good = M.T @ M + np.eye(n)
+    bad = good.copy()
+    bad[100, 100] = -5.0
+    _, info = z.potrf(dev(np.stack([good, bad])))
+    assert info[0] == 0 and info[1] > 0
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 300])
+def test_trtri(z, n):
+    rng = np.random.default_rng(n + 100)
+    R = np.stack([np.triu(rng.standard_normal((n, n))) + (n ** 0.5) * np.eye(n) for _ in range(2)])
+    Ri = z.trtri(dev(R)).cpu().numpy()
+    for b in range(2):
+        ref = dense.invert_upper(R[b])
+        assert np.allclose(np.tril(Ri[b], -1), 0.0)
+        assert np.abs(Ri[b] - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("m,n", [(40, 7), (300, 150), (129, 129), (200, 65)])
+def test_structured_qr(z, m, n):
+    rng = np.random.default_rng(m + n)
+    pivots = [0.3, 1.0, 0.0, 1e-3][: 3]
+    Y = rng.standard_normal((len(pivots), m, n))
+    Rg, _ = z.structured_qr(dev(Y), pivots, form_q=False)
+    QD, QY = z.structured_qr(dev(Y), pivots, form_q=True)
+    Rg, QD, QY = Rg.cpu().numpy(), QD.cpu().numpy(), QY.cpu().numpy()
+    for b, p in enumerate(pivots):
+        S = np.vstack([p * np.eye(n), Y[b]])
+        Q = np.vstack([QD[b], QY[b]])
+        assert np.linalg.norm(Q.T @ Q - np.eye(n)) <= 1e-13 * n
+        assert np.linalg.norm(Q @ Rg[b] - S) <= 1e-13 * n * np.linalg.norm(S)
+        assert np.allclose(np.tril(Rg[b], -1), 0.0)
+        assert np.allclose(np.tril(QD[b], -1), 0.0, atol=1e-14)
+        # R agrees with the oracle's Householder QR up to row signs, and the
+        # eq. (12) product Q_top Q_bottom^T is sign independent.
+        Qo, Ro = dense.householder_qr(np.vstack([Y[b], p * np.eye(n)]))
+        s = np.sign(np.diag(Rg[b])) * np.sign(np.diag(Ro))
+        assert np.abs(Rg[b] * s[:, None] - Ro).max() <= 1e-12 * np.abs(Ro).max()
+        if p > 0:
+            assert np.abs(QY[b] @ QD[b].T - Qo[:m] @ Qo[m:].T).max() <= 1e-12

@@ -1,0 +1,139 @@
+"""End-to-end GPU parity of Zolo-PD / Zolo-SVD (C ABI) against the CPU oracle.
+
+Bar (FP64): backward error ||A - Qp H||_F / ||A||_F <= 1e-13 and
+||Qp^T Qp - I||_F / sqrt(n) <= 1e-13, the same step kinds as the oracle, and
+||H - H_oracle||_F / ||H_oracle||_F <= 1e-12 (H is well conditioned: a
+perturbation of A moves H by at most sqrt(2) times as much).  Qp itself is
+compared only where the polar factor is well posed (kappa <= 1e8), with a
+tolerance of kappa * 1e-15 per sqrt(n).
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import zolo as oz
+from paper_1806_06204_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+BAR = 1e-13
+
+
+@pytest.fixture(scope="module")
+def z():
+    import torch
+    from paper_1806_06204_amd import zolo
+    assert torch.cuda.is_available()
+    h = zolo.Zolo()
+    yield h
+    h.close()
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def run_and_compare(z, A, alpha, l, r, kappa=None, h_tol=1e-12, **opts):
+    Qp, H, info = z.pd(dev(A), alpha=alpha, l=l, r=r, compute_errors=1, **opts)
+    Qp, H = Qp.cpu().numpy(), H.cpu().numpy()
+    oopts = {}
+    if opts.get("stop_rule") in (1, "paper"):
+        oopts["stop"] = "paper"
+    if "chol_switch" in opts:
+        oopts["chol_switch"] = opts["chol_switch"]
+    Qo, Ho, io = oz.zolo_pd(A, alpha, l, r, **oopts)
+    bwd = oz.backward_error(A, Qp, H)
+    orth = oz.orthogonality(Qp)
+    dh = np.linalg.norm(H - Ho) / np.linalg.norm(Ho)
+    print(f"  gpu kinds={''.join(info['kinds'])} oracle={''.join(io['kinds'])} bwd={bwd:.2e} orth={orth:.2e} "
+          f"dH={dh:.2e} lib bwd={info['bwd_err']:.2e} orth={info['orth_err']:.2e}", flush=True)
+    assert info["status"] == 0
+    assert info["kinds"] == io["kinds"]
+    assert bwd <= BAR and orth <= BAR
+    assert abs(info["bwd_err"] - bwd) <= 1e-15 + 0.1 * bwd
+    assert dh <= h_tol
+    if kappa is not None and kappa <= 1e8:
+        dq = np.linalg.norm(Qp - Qo) / math.sqrt(A.shape[1])
+        assert dq <= max(1e-13, kappa * 1e-15), dq
+    return info, io
+
+
+def test_small_config(z):
+    cfg = W.config_small()
+    info, io = run_and_compare(z, cfg["A"], cfg["alpha"], cfg["l"], cfg["r"], kappa=1e8)
+    assert info["kinds"] == ["Q", "C", "C"]
+    assert np.allclose(info["ls"], io["ls"], rtol=1e-12)
+
+
+def test_cholesky_only_schedule(z):
+    A = W.svd_matrix(256, 128, 10.0, 1100, 2100)[0]
+    info, _ = run_and_compare(z, A, 1.0, 0.1, 3, kappa=10.0)
+    assert set(info["kinds"]) == {"C"}
+
+
+def test_paper_stop_rule(z):
+    cfg = W.config_small()
+    run_and_compare(z, cfg["A"], 1.0, cfg["l"], 3, kappa=1e8, stop_rule=1)
+
+
+@pytest.mark.parametrize("m,n,kappa,r", [(200, 77, 1e4, 2), (65, 65, 1e6, 4), (130, 1, 1.0, 1),
+                                         (300, 150, 1e12, 5), (96, 96, 1e16, 8)])
+def test_ragged_shapes(z, m, n, kappa, r):
+    A = W.svd_matrix(m, n, kappa, 1200 + m, 2200 + n)[0]
+    run_and_compare(z, A, 1.0, 1.0 / kappa, r, kappa=kappa)
+
+
+def test_kappa_1e16_n512(z):
+    A = W.svd_matrix(512, 512, 1e16, 1300, 2300)[0]
+    info, io = run_and_compare(z, A, 1.0, 1e-16, 8)
+    assert info["kinds"][:2] == ["Q", "C"]
+
+
+def test_estimated_alpha_and_l(z):
+    A = W.sparse_pattern(256, bandwidth=16, p=0.01, seed=3001)
+    Qp, H, info = z.pd(dev(A), compute_errors=1)
+    Qo, Ho, io = oz.zolo_pd(A)
+    assert info["status"] == 0
+    assert info["alpha"] == pytest.approx(io["alpha"], rel=1e-8)
+    assert info["l0"] == pytest.approx(io["l0"], rel=1e-6)
+    assert info["r"] == io["r"]
+    Qp, H = Qp.cpu().numpy(), H.cpu().numpy()
+    assert oz.backward_error(A, Qp, H) <= BAR and oz.orthogonality(Qp) <= BAR
+    assert np.linalg.norm(H - Ho) / np.linalg.norm(Ho) <= 1e-12
+
+
+def test_failure_modes(z):
+    cfg = W.config_small()
+    Qp, H, info = z.pd(dev(cfg["A"]), alpha=1.0, l=cfg["l"], r=3, max_iter=1, check=False)
+    assert info["status"] == 1 and info["iters"] == 1
+    bad = cfg["A"].copy()
+    bad[3, 4] = np.inf
+    _, _, info = z.pd(dev(bad), alpha=1.0, l=1e-8, r=3, check=False)
+    assert info["status"] == 2
+    with pytest.raises(ValueError):
+        z.pd(dev(cfg["A"].T), alpha=1.0, l=1e-8, r=3)
+    with pytest.raises(ValueError):
+        z.pd(dev(cfg["A"]), alpha=1.0, l=1e-8, r=9)
+    A = W.svd_matrix(40, 20, 10.0, 71, 72)[0]
+    A[:, 7] = 0.0
+    Qp, _, info = z.pd(dev(A), alpha=1.0, l=1e-3, r=3, check=False)
+    assert info["status"] == 1
+
+
+def test_forced_cholesky_breakdown_falls_back(z):
+    A = W.svd_matrix(100, 100, 1e16, 1400, 2400)[0]
+    Qp, H, info = z.pd(dev(A), alpha=1.0, l=1e-16, r=8, chol_switch=1e300, compute_errors=1)
+    assert info["chol_fallbacks"] >= 1 and info["kinds"][0] == "Q"
+    assert info["status"] == 0 and info["bwd_err"] <= BAR and info["orth_err"] <= BAR
+
+
+def test_svd(z):
+    A, U, s, V = W.svd_matrix(90, 60, 1e6, 1500, 2500)
+    Uc, S, Vc, info = z.svd(dev(A), alpha=1.0, l=1e-6, r=4)
+    Uc, Vc = Uc.cpu().numpy(), Vc.cpu().numpy()
+    assert info["status"] == 0
+    assert np.allclose(S, s, rtol=1e-10, atol=1e-15)
+    assert oz.svd_residual_paper(A, Uc, S, Vc) <= 1e-13
+    assert oz.orth_paper(Uc) <= 1e-15 and oz.orth_paper(Vc) <= 1e-15

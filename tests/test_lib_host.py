@@ -1,0 +1,79 @@
+"""CPU-side checks of the native library: it loads, exports every symbol the
+headers declare, and its host-only coefficient routine (zolo_coeffs) agrees
+with the oracle.  No GPU work is launched here."""
+
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import coeffs as oc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for h in ("zolo.h", "zolo_blocks.h"):
+        txt = open(os.path.join(ROOT, "include", h)).read()
+        names += re.findall(r"^\s*(?:int|void)\s+(zolo_\w+)\s*\(", txt, flags=re.M)
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1806_06204_amd import zolo
+    if not os.path.exists(zolo.LIB_PATH):
+        pytest.skip("libzolo.so not built")
+    return zolo.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_lists_all_declared(lib):
+    from paper_1806_06204_amd import zolo
+    assert sorted(declared_functions()) == sorted(zolo.EXPORTS)
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 5, 8])
+def test_coeffs_match_oracle(lib, r):
+    from paper_1806_06204_amd import zolo
+    for l in [1e-20, 1e-16, 1e-8, 1e-3, 0.2, 0.7, 0.71, 0.95, 1 - 1e-12, 1.0]:
+        got = zolo.coeffs(l, r)
+        ref = oc.coefficients(l, r)
+        assert np.allclose(got["c"], ref["c"], rtol=2e-14, atol=0), (l, r)
+        assert np.allclose(got["a"], ref["a"], rtol=1e-12, atol=0), (l, r)
+        assert got["mhat"] == pytest.approx(ref["mhat"], rel=1e-13)
+        assert abs((1 - got["l_next"]) - (1 - ref["l_next"])) <= 1e-13 * max(1e-300, 1 - ref["l_next"]) + 4e-16
+
+
+def test_coeffs_rejects_bad_arguments(lib):
+    from paper_1806_06204_amd import zolo
+    with pytest.raises(ValueError):
+        zolo.coeffs(0.0, 3)
+    with pytest.raises(ValueError):
+        zolo.coeffs(0.5, 9)
+    with pytest.raises(ValueError):
+        zolo.coeffs(1.5, 2)
+
+
+def test_table1_through_library(lib):
+    # The library's l-update reproduces the paper's Table 1 as well.
+    import json
+    from paper_1806_06204_amd import zolo
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "table1_iterations.json")))
+    for rs, row in g["iterations"].items():
+        got = []
+        for kap in g["kappa"]:
+            l, k = 1.0 / kap, 0
+            while l < 1 - 1e-15 and k < 20:
+                l = zolo.coeffs(l, int(rs))["l_next"]
+                k += 1
+            got.append(k)
+        assert got == row, rs
