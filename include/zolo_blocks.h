@@ -36,20 +36,20 @@ int zolo_dpotrf_batched(zolo_handle h, int n, double* Z, int ldz, long long stri
 int zolo_dtrtri_batched(zolo_handle h, int n, const double* R, int ldr, long long strideR,
                         double* Rinv, int ldi, long long strideI, int batch);
 
-/* Structured Householder QR of the stacked [p_b I; Y_b] (n + m rows, n
- * columns), b < batch <= 16, m >= 1, n >= 1 (Section 3.1: each reflector has
- * m + 1 nonzeros, each block of 64 reflectors m + 64 live rows).  The
- * identity block is placed on top; the pair is the paper's
- * [X; sqrt(c_{2j-1}) I] of eq. (12) with rows reordered, which leaves
- * Q_{j1} Q_{j2}^T unchanged.
- * pivots (host, batch entries) are the p_b >= 0.  On entry Y_b (m x n) holds
- * the dense block; D_b (n x n) is overwritten.  On exit, form_q == 0: D_b
- * holds R_b (upper triangular, zero below) and Y_b the Y-part of the
- * Householder vectors; form_q != 0: D_b holds Q_D (n x n, upper triangular)
- * and Y_b holds Q_Y (m x n) with [Q_D; Q_Y] R = [p_b I; Y_b].
- * With p_b = 0 this is a Householder QR of Y_b alone (R in D_b). */
-int zolo_structured_qr_batched(zolo_handle h, int m, int n, const double* pivots, double* Y, int ldy,
-                               long long strideY, double* D, int ldd, long long strideD, int batch, int form_q);
+/* Structured Householder QR of the stacked [Y_b; p_b I] ((m + n) x n), or a
+ * plain Householder QR of Y_b (m x n, m >= n) when pivots is NULL, for
+ * b < batch <= 16 (Section 3.1 / eq. (12): with Y = X and p = sqrt(c_{2j-1})
+ * this is the factorisation of a QR-type Zolo-PD step; each block of 64
+ * reflectors acts on the m + 64 contiguous rows [p0, m + p0 + 64)).
+ * M_b = M + b * strideM has leading dimension ldm >= m + n (stacked) or >= m
+ * (plain).  On entry rows 0..m-1 of M_b hold Y_b; the call writes p_b I into
+ * rows m..m+n-1.  pivots (host, batch entries) must be >= 0.
+ * On exit: if R != NULL, R_b = R + b * strideR (n x n, ldr >= n) receives the
+ * upper-triangular factor (zeros below); if form_q != 0, M_b holds the thin
+ * Q with [Q_1; Q_2] R = M_b (Q_2, the bottom n x n block, is upper
+ * triangular), else M_b holds the Householder vectors. */
+int zolo_structured_qr_batched(zolo_handle h, int m, int n, const double* pivots, double* M, int ldm,
+                               long long strideM, double* R, int ldr, long long strideR, int batch, int form_q);
 
 #ifdef __cplusplus
 }

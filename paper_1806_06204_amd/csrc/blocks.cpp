@@ -104,41 +104,43 @@ int zolo_dtrtri_batched(zolo_handle h, int n, const double* R, int ldr, long lon
                                         h->stream));
 }
 
-int zolo_structured_qr_batched(zolo_handle h, int m, int n, const double* pivots, double* Y, int ldy,
-                               long long strideY, double* D, int ldd, long long strideD, int batch, int form_q) {
+int zolo_structured_qr_batched(zolo_handle h, int m, int n, const double* pivots, double* M, int ldm,
+                               long long strideM, double* R, int ldr, long long strideR, int batch, int form_q) {
     if (!h) return -1;
     if (m < 1) return -2;
-    if (n < 1) return -3;
-    if (!pivots) return -4;
-    if (!Y) return -5;
-    if (ldy < m) return -6;
-    if (!D) return -8;
-    if (ldd < n) return -9;
+    if (n < 1 || (!pivots && n > m)) return -3;
+    if (!M) return -5;
+    const int e = pivots ? n : 0;
+    if (ldm < m + e) return -6;
+    if (R && ldr < n) return -9;
     if (batch < 1 || batch > kMaxInlineAlpha) return -11;
-    for (int b = 0; b < batch; ++b)
-        if (!(pivots[b] >= 0.0)) return -4;
+    if (pivots)
+        for (int b = 0; b < batch; ++b)
+            if (!(pivots[b] >= 0.0)) return -4;
     const int npanels = (n + kPanelNB - 1) / kPanelNB;
-    const int maxG = std::max(1, std::min((m + 63) / 64, h->panel_coresident));
+    const size_t blk = (size_t)batch * npanels * kPanelNB * kPanelNB;
+    const size_t part = qr_partials_elems(m, e, batch, h->panel_coresident);
     size_t off = 0;
-    const size_t need = 8 * 256 + sizeof(double) * ((size_t)batch * kPanelNB * n +
-                                                    (size_t)batch * npanels * kPanelNB * kPanelNB +
-                                                    (size_t)batch * 2 * maxG * kPanelNB) +
+    const size_t need = 8 * 256 + sizeof(double) * ((size_t)batch * kPanelNB * n + 2 * blk +
+                                                    (size_t)batch * kPanelNB * kPanelNB + part) +
                         sizeof(unsigned) * (size_t)batch * npanels + 64;
     if (int rc = grow(h, need)) return rc;
     QrWork w;
     w.W = (double*)bump(h->arena, off, sizeof(double) * (size_t)batch * kPanelNB * n);
-    w.T = (double*)bump(h->arena, off, sizeof(double) * (size_t)batch * npanels * kPanelNB * kPanelNB);
-    w.partials = (double*)bump(h->arena, off, sizeof(double) * (size_t)batch * 2 * maxG * kPanelNB);
+    w.T = (double*)bump(h->arena, off, sizeof(double) * blk);
+    w.Rd = (double*)bump(h->arena, off, sizeof(double) * blk);
+    w.S = (double*)bump(h->arena, off, sizeof(double) * (size_t)batch * kPanelNB * kPanelNB);
+    w.partials = (double*)bump(h->arena, off, sizeof(double) * part);
     w.counters = (unsigned*)bump(h->arena, off, sizeof(unsigned) * (size_t)batch * npanels);
     w.error_flag = (int*)bump(h->arena, off, 64);
     w.max_coresident = h->panel_coresident;
     hipStream_t st = h->stream;
-    hipError_t e = hipMemsetAsync(w.error_flag, 0, sizeof(int), st);
-    for (int b = 0; b < batch && e == hipSuccess; ++b)
-        e = hipMemset2DAsync(D + b * strideD, sizeof(double) * ldd, 0, sizeof(double) * n, n, st);
-    if (e == hipSuccess) e = structured_geqrf(m, n, Y, ldy, strideY, D, ldd, strideD, pivots, batch, w, st);
-    if (e == hipSuccess && form_q) e = structured_orgqr(m, n, Y, ldy, strideY, D, ldd, strideD, batch, w, st);
-    if (int rc = sync_status(h, e)) return rc;
+    hipError_t err = hipMemsetAsync(w.error_flag, 0, sizeof(int), st);
+    if (err == hipSuccess && pivots) err = stack_init(m, n, nullptr, ldm, M, ldm, strideM, pivots, batch, st);
+    if (err == hipSuccess) err = structured_geqrf(m, e, n, M, ldm, strideM, batch, w, st);
+    if (err == hipSuccess && R) err = assemble_r(n, M, ldm, strideM, batch, w, R, ldr, strideR, st);
+    if (err == hipSuccess && form_q) err = structured_orgqr(m, e, n, M, ldm, strideM, batch, w, st);
+    if (int rc = sync_status(h, err)) return rc;
     int flag = 0;
     if (hipMemcpy(&flag, w.error_flag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return ZOLO_HIP;
     return flag ? ZOLO_KERNEL : 0;

@@ -9,7 +9,9 @@
 // result; each wave owns (BM/2) x (BN/2) as a grid of 16 x 16 MFMA blocks held
 // in accumulator registers.  K is walked in BK = 16 slices staged through LDS
 // (k-major, so that a fragment load is 16 consecutive doubles); the next slice
-// is fetched into registers while the current one feeds the MFMAs.  Tiles are
+// is fetched into registers while the current one feeds the MFMAs.
+// Lane layout of v_mfma_f64_16x16x4f64 (lane l, accumulator element e):
+// A[l % 16][l / 16], B[l / 16][l % 16], D[l / 16 + 4 e][l % 16].  Tiles are
 // ordered in groups of 8 tile-rows and the workgroup ids are remapped so that
 // neighbouring tiles run on the same XCD and reuse its L2.
 #include "common.hpp"
@@ -145,7 +147,7 @@ __global__ __launch_bounds__(256, (BM * BN >= 128 * 128) ? 1 : 2) void dgemm_ker
         for (int j = 0; j < FN; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int gi = row0 + wm + i * 16 + (lane >> 4) * 4 + e;
+                const int gi = row0 + wm + i * 16 + (lane >> 4) + 4 * e;
                 const int gj = col0 + wn + j * 16 + (lane & 15);
                 bool ok = gi < d.m && gj < d.n;
                 if (fl & kCStoreUpper) ok = ok && gi <= gj;

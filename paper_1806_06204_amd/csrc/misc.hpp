@@ -51,25 +51,42 @@ constexpr int kPanelNB = 64;
 
 struct QrWork {
     double* W = nullptr;          // batch * kPanelNB * n doubles
-    double* T = nullptr;          // batch * npanels * kPanelNB * kPanelNB doubles
-    double* partials = nullptr;   // batch * 2 * maxG * kPanelNB doubles
+    double* T = nullptr;          // batch * npanels * kPanelNB^2 doubles
+    double* Rd = nullptr;         // batch * npanels * kPanelNB^2 doubles (R diagonal blocks)
+    double* S = nullptr;          // batch * kPanelNB^2 doubles
+    double* partials = nullptr;   // batch * 2 * maxG * 2 * kPanelNB doubles
     unsigned* counters = nullptr; // batch * npanels
     int* error_flag = nullptr;    // 1 int
     int max_coresident = 0;       // workgroups of the panel kernel that fit at once
 };
 
-// Structured Householder QR of the stacked [D_b; Y_b] with D_b = pivot_b * I
-// (n x n) on top and Y_b (m x n) below, for b < batch (Section 3.1 / eq. (12)).
-// On entry Y_b holds the dense block; D_b must be zero.  On exit Y_b holds
-// the lower parts of the Householder vectors (their D-part is the identity),
-// D_b holds R (upper triangular) and work.T the block-reflector factors.
-// rows_live(p) = m for every panel (live rows m + NB per panel).
-hipError_t structured_geqrf(int m, int n, double* Y, long long ldy, long long sy, double* D, long long ldd,
-                            long long sd, const double* pivots, int batch, const QrWork& w, hipStream_t st);
-// Forms the explicit thin Q = [Q_D; Q_Y] in place of (D_b, Y_b) from the
-// output of structured_geqrf (reflectors applied last panel first).  Q_D is
-// upper triangular.
-hipError_t structured_orgqr(int m, int n, double* Y, long long ldy, long long sy, double* D, long long ldd,
-                            long long sd, int batch, const QrWork& w, hipStream_t st);
+// Doubles each QrWork array needs for m x n, `batch` matrices, e extra rows.
+inline size_t qr_partials_elems(int m, int e, int batch, int max_coresident) {
+    int G = (m + e + 255) / 256;
+    int cap = max_coresident / (batch > 0 ? batch : 1);
+    if (cap < 1) cap = 1;
+    if (G > cap) G = cap;
+    if (G < 1) G = 1;
+    return (size_t)batch * 2 * (G + 1) * 2 * kPanelNB;
+}
+
+// M_b[0:m] = X (ld ldx; X null: leave the dense block), M_b[m:m+n] = pivots[b] * I, b < batch <= 16.
+hipError_t stack_init(int m, int n, const double* X, long long ldx, double* M, long long ld, long long sm,
+                      const double* pivots, int batch, hipStream_t st);
+// Householder QR of M_b ((m + e) x n, e = n for the stacked [Y; p I] of
+// eq. (12) (Section 3.1: each block of 64 reflectors acts on the m + 64
+// contiguous rows [p0, m + p0 + 64)), or e = 0 for a plain QR of an m x n
+// matrix).  On exit M_b holds the Householder vectors (explicit unit lower
+// trapezoidal), w.T the block-reflector factors and w.Rd the diagonal blocks of
+// R; the rest of R is in the upper part of M_b (see assemble_r).
+hipError_t structured_geqrf(int m, int e, int n, double* M, long long ld, long long sm, int batch,
+                            const QrWork& w, hipStream_t st);
+// Overwrites the output of structured_geqrf with the explicit thin Q
+// ((m + e) x n); for e = n the bottom n x n block of Q is upper triangular.
+hipError_t structured_orgqr(int m, int e, int n, double* M, long long ld, long long sm, int batch,
+                            const QrWork& w, hipStream_t st);
+// R_b (n x n, zeros below) from the output of structured_geqrf.
+hipError_t assemble_r(int n, const double* M, long long ld, long long sm, int batch, const QrWork& w, double* R,
+                      long long ldr, long long sr, hipStream_t st);
 
 }  // namespace zolo

@@ -1,24 +1,31 @@
-// Structured Householder QR of the stacked matrices [D_b; Y_b], D_b = p_b I
-// (n x n, the identity block of eq. (12) scaled by p_b = sqrt(c_{2b-1})),
-// Y_b dense m x n, for all b at once (Section 3.1 of the paper).
+// Structured Householder QR of the stacked matrices M_b = [Y_b; p_b I]
+// ((m + n) x n, the [X; sqrt(c_{2j-1}) I] of eq. (12)) for all b at once, and
+// the plain Householder QR of an m x n matrix (no identity block), on gfx950.
 //
-// Storage puts the identity block on top.  Then every reflector pivots on its
-// own row of D and touches that row plus the m rows of Y: it has m + 1
-// nonzeros, its D-part is a unit vector, and a block of NB = 64 reflectors
-// has m + NB live rows, as in the paper's structured routines.  V = [I; Y_V],
-// so only Y_V is stored (in place of Y) and V^T V = I + Y_V^T Y_V.
+// Structure (Section 3.1 of the paper).  Reflector k pivots on row k of the
+// dense block; below the pivot it touches the dense rows k+1..m-1 and the
+// identity-block rows m..m+k (the identity block fills in upper triangular as
+// the factorisation proceeds).  With M stored as one column-major array, a
+// block of NB = 64 reflectors starting at column p0 therefore lives on the
+// contiguous rows [p0, m + p0 + NB): m + NB live rows instead of the m + n - p0
+// of a dense QR.  The identity rows stay below the dense rows on purpose:
+// pivoting on the small rows p I first (identity block on top) loses row-wise
+// backward stability when p is tiny, e.g. 1e-10 backward error at kappa = 1e8.
 //
 // Panel: one cooperative launch per panel factors all b together.  Each
-// matrix gets G workgroups, each owning a slab of Y rows; per column k the
-// workgroups apply reflector k-1 to their rows and accumulate the dot
-// products of column k with every panel column in the same pass, so one
-// cross-workgroup reduction per column gives the norm, the new R row and the
-// next column of T (compact WY, Q = I - V T V^T).  The reduction is
-// deterministic (fixed summation order) and its barrier has a bounded wait.
+// matrix gets G workgroups, each owning a slab of the panel's live rows.  For
+// column k a workgroup applies reflector k-1 to its rows and, in the same pass,
+// accumulates the dot products of column k (below the pivot) with every panel
+// column and picks up the pivot row; one cross-workgroup reduction of these
+// 2 NB numbers gives the norm, the update coefficients of the remaining
+// columns and the next column of T (compact WY, Q = I - V T V^T).  The
+// reduction sums partials in a fixed order; its barrier waits a bounded time.
+// On exit the panel's top block holds V explicitly (unit diagonal, zeros above)
+// and the R diagonal block is saved apart.
 //
-// Trailing update and Q formation are three GEMMs per panel on the MFMA
-// kernel:  W = Y_V^T C_Y,  C_D = -T^T W (written into R's row block),
-// C_Y += Y_V C_D.  ORGQR applies the panels last to first to [I; 0].
+// Trailing update and Q formation are GEMMs on the MFMA kernel over the live
+// rows:  W = V^T C,  W <- T^T W,  C -= V W  (ORGQR: T instead of T^T, panels
+// last to first, then the panel's own columns = [I; 0] - V (T V_top^T)).
 #include "misc.hpp"
 
 namespace zolo {
@@ -29,73 +36,81 @@ constexpr int kPT = 256;                 // threads per panel workgroup
 constexpr int kColsPerWave = kNB / 4;    // panel columns owned by each wave
 
 struct PanelArgs {
-    int m, nb, G, rows_per_wg;
-    double* Y; long long ldy, sy;        // column p0 of Y_0
-    double* D; long long ldd, sd;        // D_0[p0][p0]
+    int L, nb, G, rows_per_wg;
+    double* P; long long ld, sp;         // panel top-left (row p0, column p0) of matrix 0
     double* T; long long st;             // T_b, kNB x kNB column-major
-    double* partials;                    // [batch][2][G][kNB]
+    double* Rd; long long srd;           // R diagonal block out, kNB x kNB
+    double* partials;                    // [batch][2][G][2 kNB]
     unsigned* counters;                  // [batch]
     int* error_flag;
     unsigned spin_limit;
-    double pivot[kMaxInlineAlpha];
 };
 
 __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
     __shared__ double sT[kNB][kNB + 1];
-    __shared__ double s_d[kNB], s_coef[kNB], s_wsum[kNB], s_z[kNB];
+    __shared__ double s_d[kNB], s_pr[kNB], s_coef[kNB], s_z[kNB], s_w[2 * kNB];
     const int g = blockIdx.x % a.G, b = blockIdx.x / a.G;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const long long ldy = a.ldy;
-    double* __restrict__ Y = a.Y + b * a.sy;
+    const long long ld = a.ld;
+    double* __restrict__ P = a.P + b * a.sp;
     const int r0 = g * a.rows_per_wg;
-    const int r1 = min(a.m, r0 + a.rows_per_wg);
+    const int r1 = min(a.L, r0 + a.rows_per_wg);
     const int nb = a.nb;
     for (int e = tid; e < kNB * kNB; e += kPT) sT[e / kNB][e % kNB] = 0.0;
     if (tid < kNB) s_coef[tid] = 0.0;
     __syncthreads();
-    const double alpha = a.pivot[b];
     unsigned* ctr = a.counters + b;
 
     for (int k = 0; k < nb; ++k) {
-        // Phase A: apply reflector k-1 to columns > k of this slab (each wave
-        // owns columns wave, wave+4, ...) and accumulate dots with column k.
-        double acc[kColsPerWave];
+        // Phase A: reflector k-1 on the columns > k (rows >= k-1), dot products
+        // of column k below the pivot with every panel column, pivot row values.
+        double acc[kColsPerWave], prv[kColsPerWave];
 #pragma unroll
-        for (int q = 0; q < kColsPerWave; ++q) acc[q] = 0.0;
+        for (int q = 0; q < kColsPerWave; ++q) acc[q] = prv[q] = 0.0;
         const double ck = k > 0 ? s_coef[k] : 0.0;
-        for (int row = r0 + lane; row < r1; row += 64) {
-            const double vprev = k > 0 ? Y[row + (k - 1) * ldy] : 0.0;
-            const double yk = Y[row + k * ldy] - ck * vprev;
+        const int lo = max(r0, k > 0 ? k - 1 : 0);
+        for (int row = lo + lane; row < r1; row += 64) {
+            const double vprev = k > 0 ? (row == k - 1 ? 1.0 : P[row + (k - 1) * ld]) : 0.0;
+            const double xk = P[row + k * ld] - ck * vprev;
 #pragma unroll
             for (int q = 0; q < kColsPerWave; ++q) {
                 const int i = wave + 4 * q;
                 if (i < nb) {
                     double val;
-                    if (i == k) {
-                        val = yk;
+                    if (i < k) {
+                        val = P[row + i * ld];
+                    } else if (i == k) {
+                        val = xk;
                     } else {
-                        val = Y[row + i * ldy];
-                        if (i > k && k > 0) {
+                        val = P[row + i * ld];
+                        if (k > 0) {
                             val -= s_coef[i] * vprev;
-                            Y[row + i * ldy] = val;
+                            P[row + i * ld] = val;
                         }
                     }
-                    acc[q] += yk * val;
+                    if (row > k) acc[q] += xk * val;
+                    else if (row == k) prv[q] = val;
                 }
             }
         }
 #pragma unroll
         for (int q = 0; q < kColsPerWave; ++q) {
             const double s = wave_sum(acc[q]);
+            const double p = wave_sum(prv[q]);   // only the lane holding the pivot row is nonzero
             const int i = wave + 4 * q;
-            if (lane == 0 && i < nb) s_wsum[i] = s;
+            if (lane == 0 && i < nb) {
+                s_w[i] = s;
+                s_w[kNB + i] = p;
+            }
         }
         __syncthreads();
 
-        // Phase B: publish this slab's partial dots, wait for the other slabs
-        // of the same matrix, and sum all partials in a fixed order.
-        double* part = a.partials + (((long long)b * 2 + (k & 1)) * a.G + g) * kNB;
-        if (tid < nb) __hip_atomic_store(&part[tid], s_wsum[tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // Phase B: publish, wait for the other slabs of this matrix, sum in order.
+        double* part = a.partials + (((long long)b * 2 + (k & 1)) * a.G + g) * (2 * kNB);
+        if (tid < nb) {
+            __hip_atomic_store(&part[tid], s_w[tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&part[kNB + tid], s_w[kNB + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         __syncthreads();
         if (tid == 0) {
             __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -110,23 +125,35 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
             }
         }
         __syncthreads();
-        if (tid < nb) {
-            const double* pb = a.partials + ((long long)b * 2 + (k & 1)) * a.G * kNB;
+        if (tid < 2 * nb) {
+            const int idx = tid < nb ? tid : kNB + (tid - nb);
+            const double* pb = a.partials + ((long long)b * 2 + (k & 1)) * a.G * (2 * kNB);
             double s = 0.0;
             for (int gg = 0; gg < a.G; ++gg)
-                s += __hip_atomic_load(&pb[gg * kNB + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s_d[tid] = s;
+                s += __hip_atomic_load(&pb[gg * (2 * kNB) + idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (tid < nb) s_d[tid] = s;
+            else s_pr[tid - nb] = s;
         }
         __syncthreads();
 
-        // Phase C: reflector k.  x = [alpha; y_k], beta = -sqrt(alpha^2 + |y_k|^2)
-        // (alpha > 0, so alpha - beta never cancels), v = [1; y_k/(alpha-beta)].
-        const double beta = -sqrt(alpha * alpha + s_d[k]);
-        const double tau = (beta - alpha) / beta;
-        const double scale = 1.0 / (alpha - beta);
+        // Phase C: reflector k on x = [alpha; below], beta = -sign(alpha) |x|,
+        // v = [1; below / (alpha - beta)]  (no cancellation in alpha - beta).
+        const double alpha = s_pr[k], s2 = s_d[k];
+        double beta, tau, scale;
+        if (s2 == 0.0) {
+            beta = alpha;
+            tau = 0.0;
+            scale = 0.0;
+        } else {
+            const double nrm = sqrt(alpha * alpha + s2);
+            beta = alpha >= 0.0 ? -nrm : nrm;
+            tau = (beta - alpha) / beta;
+            scale = 1.0 / (alpha - beta);
+        }
         if (tid < nb) {
-            if (tid > k) s_coef[tid] = tau * scale * s_d[tid];   // tau * (v_k^T column)
-            if (tid < k) s_z[tid] = scale * s_d[tid];            // v_i^T v_k
+            const double w = s_pr[tid] + scale * s_d[tid];  // v_k^T col (tid > k) or v_tid^T v_k (tid < k)
+            if (tid > k) s_coef[tid] = tau * w;
+            if (tid < k) s_z[tid] = w;
         }
         __syncthreads();
         if (tid < k) {
@@ -135,17 +162,25 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
             sT[tid][k] = -tau * s;
         }
         if (tid == 0) sT[k][k] = tau;
-        if (g == 0 && tid < nb) {
-            double* Db = a.D + b * a.sd;
-            if (tid == k) Db[k + k * a.ldd] = beta;
-            if (tid > k) Db[k + tid * a.ldd] = -s_coef[tid];
-        }
-        // Phase D: store v_k = scale * (column k after reflector k-1).
-        for (int row = r0 + tid; row < r1; row += kPT) {
-            const double vprev = k > 0 ? Y[row + (k - 1) * ldy] : 0.0;
-            Y[row + k * ldy] = scale * (Y[row + k * ldy] - ck * vprev);
+        // Phase D: column k: R entry on row k-1, beta on the pivot, v below.
+        for (int row = max(r0, k > 0 ? k - 1 : 0) + tid; row < r1; row += kPT) {
+            const double vprev = k > 0 ? (row == k - 1 ? 1.0 : P[row + (k - 1) * ld]) : 0.0;
+            const double x = P[row + k * ld] - ck * vprev;
+            P[row + k * ld] = row == k ? beta : (row > k ? scale * x : x);
         }
         __syncthreads();
+    }
+    // Save the R diagonal block; make V's top block explicit (1 on the
+    // diagonal, 0 above) so the GEMMs can use the stored panel as V.
+    double* Rd = a.Rd + b * a.srd;
+    for (int e = tid; e < kNB * kNB; e += kPT) {
+        const int i = e % kNB, j = e / kNB;
+        if ((i >= r0 && i < r1) || (g == 0 && i >= a.L)) {
+            const bool in = i < nb && j < nb && i < a.L;
+            const double v = in ? P[i + j * ld] : 0.0;
+            Rd[e] = (in && i <= j) ? v : 0.0;
+            if (in && i <= j) P[i + j * ld] = (i == j) ? 1.0 : 0.0;
+        }
     }
     if (g == 0) {
         double* Tb = a.T + b * a.st;
@@ -153,12 +188,50 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
     }
 }
 
-// D_b[p0+i][p0+j] = delta_ij - T_b[i][j] for the panel's diagonal block.
-__global__ void i_minus_t_kernel(int nb, double* D, long long ldd, long long sd, const double* T, long long st) {
-    const int b = blockIdx.x;
-    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
-        const int i = e % nb, j = e / nb;
-        D[b * sd + i + j * ldd] = (i == j ? 1.0 : 0.0) - T[b * st + i + j * kNB];
+// ORGQR panel fix-up: rows above the panel become 0 and the top block gets +I.
+__global__ void orgqr_fix_kernel(int p0, int nb, double* M, long long ld, long long sm) {
+    const int b = blockIdx.y;
+    double* Mb = M + b * sm;
+    const int total = (p0 + nb) * nb;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+        const int i = e % (p0 + nb), j = e / (p0 + nb);
+        double* p = Mb + i + (long long)(p0 + j) * ld;
+        if (i < p0) *p = 0.0;
+        else if (i - p0 == j) *p += 1.0;
+    }
+}
+
+// M_b[0:m] = X (skipped when X is null), M_b[m:m+n] = p_b I.
+__global__ void stack_init_kernel(int m, int n, const double* __restrict__ X, long long ldx,
+                                  double* __restrict__ M, long long ld, long long sm, ShiftArgs piv) {
+    const long long rows = (long long)m + n;
+    const long long total = rows * n;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long j = e / rows, i = e - j * rows;
+        if (i < m && X == nullptr) continue;  // dense block already in place
+        const double x = i < m ? X[i + j * ldx] : 0.0;
+        for (int b = 0; b < piv.batch; ++b)
+            M[b * sm + i + j * ld] = i < m ? x : (i - m == j ? piv.shift[b] : 0.0);
+    }
+}
+
+// R_b (n x n) from the factored M_b: off-diagonal blocks from M's upper part,
+// diagonal blocks from the saved Rd, zeros below the diagonal.
+__global__ void assemble_r_kernel(int n, const double* __restrict__ M, long long ld, long long sm,
+                                  const double* __restrict__ Rd, long long srd_b, double* __restrict__ R,
+                                  long long ldr, long long sr) {
+    const int b = blockIdx.y;
+    const long long total = (long long)n * n;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long j = e / n, i = e - j * n;
+        double v = 0.0;
+        if (i <= j) {
+            const long long pi = i / kNB, pj = j / kNB;
+            v = pi == pj ? Rd[b * srd_b + pi * kNB * kNB + (i % kNB) + (j % kNB) * kNB] : M[b * sm + i + j * ld];
+        }
+        R[b * sr + i + j * ldr] = v;
     }
 }
 
@@ -166,21 +239,22 @@ struct Geometry {
     int G, rows;
 };
 
-Geometry panel_geometry(int m, int batch, int max_coresident) {
-    // Aim for ~256 rows per workgroup and keep every workgroup resident.
-    int G = (m + 255) / 256;
+Geometry panel_geometry(int L, int batch, int max_coresident) {
+    // ~256 rows per workgroup, at least 64, every workgroup resident.
+    int G = (L + 255) / 256;
     if (G < 1) G = 1;
     int cap = max_coresident / batch;
     if (cap < 1) cap = 1;
     if (G > cap) G = cap;
-    int rows = (m + G - 1) / G;
-    G = (m + rows - 1) / rows;
+    int rows = (L + G - 1) / G;
+    if (rows < 64) rows = 64;
+    G = (L + rows - 1) / rows;
     return {G, rows};
 }
 
-hipError_t launch_panel(PanelArgs& pa, int batch, hipStream_t st) {
-    void* args[] = {&pa};
-    return hipLaunchCooperativeKernel((const void*)panel_kernel, dim3(pa.G * batch), dim3(kPT), args, 0, st);
+inline int live_rows(int m, int e, int p0, int nb) {
+    const int end = m + p0 + nb < m + e ? m + p0 + nb : m + e;
+    return end - p0;
 }
 
 }  // namespace
@@ -194,112 +268,141 @@ int panel_max_coresident() {
     return per_cu * cus;
 }
 
-hipError_t structured_geqrf(int m, int n, double* Y, long long ldy, long long sy, double* D, long long ldd,
-                            long long sd, const double* pivots, int batch, const QrWork& w, hipStream_t st) {
+hipError_t stack_init(int m, int n, const double* X, long long ldx, double* M, long long ld, long long sm,
+                      const double* pivots, int batch, hipStream_t st) {
     if (batch > kMaxInlineAlpha) return hipErrorInvalidValue;
+    ShiftArgs piv;
+    piv.batch = batch;
+    for (int b = 0; b < batch; ++b) piv.shift[b] = pivots[b];
+    const long long total = ((long long)m + n) * n;
+    long long grid = (total + 255) / 256;
+    if (grid > 8192) grid = 8192;
+    stack_init_kernel<<<(int)grid, 256, 0, st>>>(m, n, X, ldx, M, ld, sm, piv);
+    return hipGetLastError();
+}
+
+hipError_t assemble_r(int n, const double* M, long long ld, long long sm, int batch, const QrWork& w, double* R,
+                      long long ldr, long long sr, hipStream_t st) {
     const int npanels = (n + kNB - 1) / kNB;
-    const Geometry geo = panel_geometry(m, batch, w.max_coresident);
-    hipError_t e = hipMemsetAsync(w.counters, 0, sizeof(unsigned) * (size_t)batch * npanels, st);
-    if (e != hipSuccess) return e;
+    long long grid = ((long long)n * n + 255) / 256;
+    if (grid > 4096) grid = 4096;
+    assemble_r_kernel<<<dim3((int)grid, batch), 256, 0, st>>>(n, M, ld, sm, w.Rd, (long long)npanels * kNB * kNB,
+                                                             R, ldr, sr);
+    return hipGetLastError();
+}
+
+hipError_t structured_geqrf(int m, int e, int n, double* M, long long ld, long long sm, int batch, const QrWork& w,
+                            hipStream_t st) {
+    if (batch > kMaxInlineAlpha || batch < 1) return hipErrorInvalidValue;
+    const int npanels = (n + kNB - 1) / kNB;
+    const long long stT = (long long)npanels * kNB * kNB;
+    hipError_t err = hipMemsetAsync(w.counters, 0, sizeof(unsigned) * (size_t)batch * npanels, st);
+    if (err != hipSuccess) return err;
     for (int p = 0; p < npanels; ++p) {
         const int p0 = p * kNB;
         const int nb = n - p0 < kNB ? n - p0 : kNB;
+        const int L = live_rows(m, e, p0, nb);
+        const Geometry geo = panel_geometry(L, batch, w.max_coresident);
         PanelArgs pa;
-        pa.m = m; pa.nb = nb; pa.G = geo.G; pa.rows_per_wg = geo.rows;
-        pa.Y = Y + (long long)p0 * ldy; pa.ldy = ldy; pa.sy = sy;
-        pa.D = D + p0 + (long long)p0 * ldd; pa.ldd = ldd; pa.sd = sd;
-        pa.T = w.T + (long long)p * kNB * kNB; pa.st = (long long)npanels * kNB * kNB;
+        pa.L = L; pa.nb = nb; pa.G = geo.G; pa.rows_per_wg = geo.rows;
+        pa.P = M + p0 + (long long)p0 * ld; pa.ld = ld; pa.sp = sm;
+        pa.T = w.T + (long long)p * kNB * kNB; pa.st = stT;
+        pa.Rd = w.Rd + (long long)p * kNB * kNB; pa.srd = stT;
         pa.partials = w.partials;
         pa.counters = w.counters + (long long)p * batch;
         pa.error_flag = w.error_flag;
         pa.spin_limit = 1u << 22;
-        for (int b = 0; b < batch; ++b) pa.pivot[b] = pivots[b];
-        if ((e = launch_panel(pa, batch, st)) != hipSuccess) return e;
+        void* args[] = {&pa};
+        err = hipLaunchCooperativeKernel((const void*)panel_kernel, dim3(pa.G * batch), dim3(kPT), args, 0, st);
+        if (err != hipSuccess) return err;
         const int trail = n - p0 - nb;
         if (trail <= 0) continue;
-        double* YV = Y + (long long)p0 * ldy;
-        double* Yt = Y + (long long)(p0 + nb) * ldy;
-        double* Dt = D + p0 + (long long)(p0 + nb) * ldd;
-        // W = Y_V^T Y_trail
-        GemmDesc g1;
-        g1.m = nb; g1.n = trail; g1.k = m; g1.transa = 1;
-        g1.A = YV; g1.lda = ldy; g1.strideA = sy;
-        g1.B = Yt; g1.ldb = ldy; g1.strideB = sy;
+        double* V = M + p0 + (long long)p0 * ld;
+        double* C = M + p0 + (long long)(p0 + nb) * ld;
+        GemmDesc g1;  // W = V^T C
+        g1.m = nb; g1.n = trail; g1.k = L; g1.transa = 1;
+        g1.A = V; g1.lda = ld; g1.strideA = sm;
+        g1.B = C; g1.ldb = ld; g1.strideB = sm;
         g1.C = w.W; g1.ldc = kNB; g1.strideC = (long long)kNB * n;
         g1.batch = batch;
-        if ((e = gemm(g1, st)) != hipSuccess) return e;
-        // R row block = -T^T W
-        GemmDesc g2;
+        if ((err = gemm(g1, st)) != hipSuccess) return err;
+        GemmDesc g2;  // W <- T^T W (one tile row: in place is safe)
         g2.m = nb; g2.n = trail; g2.k = nb; g2.transa = 1;
-        g2.A = pa.T; g2.lda = kNB; g2.strideA = pa.st;
+        g2.A = pa.T; g2.lda = kNB; g2.strideA = stT;
         g2.B = w.W; g2.ldb = kNB; g2.strideB = (long long)kNB * n;
-        g2.C = Dt; g2.ldc = ldd; g2.strideC = sd;
-        g2.alpha = -1.0; g2.batch = batch; g2.flags = kALower;
-        if ((e = gemm(g2, st)) != hipSuccess) return e;
-        // Y_trail += Y_V (R row block)
-        GemmDesc g3;
-        g3.m = m; g3.n = trail; g3.k = nb;
-        g3.A = YV; g3.lda = ldy; g3.strideA = sy;
-        g3.B = Dt; g3.ldb = ldd; g3.strideB = sd;
-        g3.Cin = Yt; g3.ldcin = ldy; g3.strideCin = sy;
-        g3.C = Yt; g3.ldc = ldy; g3.strideC = sy;
-        g3.beta = 1.0; g3.batch = batch;
-        if ((e = gemm(g3, st)) != hipSuccess) return e;
+        g2.C = w.W; g2.ldc = kNB; g2.strideC = (long long)kNB * n;
+        g2.batch = batch; g2.flags = kALower;
+        if ((err = gemm(g2, st)) != hipSuccess) return err;
+        GemmDesc g3;  // C -= V W
+        g3.m = L; g3.n = trail; g3.k = nb;
+        g3.A = V; g3.lda = ld; g3.strideA = sm;
+        g3.B = w.W; g3.ldb = kNB; g3.strideB = (long long)kNB * n;
+        g3.Cin = C; g3.ldcin = ld; g3.strideCin = sm;
+        g3.C = C; g3.ldc = ld; g3.strideC = sm;
+        g3.alpha = -1.0; g3.beta = 1.0; g3.batch = batch;
+        if ((err = gemm(g3, st)) != hipSuccess) return err;
     }
     return hipSuccess;
 }
 
-hipError_t structured_orgqr(int m, int n, double* Y, long long ldy, long long sy, double* D, long long ldd,
-                            long long sd, int batch, const QrWork& w, hipStream_t st) {
+hipError_t structured_orgqr(int m, int e, int n, double* M, long long ld, long long sm, int batch, const QrWork& w,
+                            hipStream_t st) {
     const int npanels = (n + kNB - 1) / kNB;
     const long long stT = (long long)npanels * kNB * kNB;
-    hipError_t e;
+    hipError_t err;
     for (int p = npanels - 1; p >= 0; --p) {
         const int p0 = p * kNB;
         const int nb = n - p0 < kNB ? n - p0 : kNB;
+        const int L = live_rows(m, e, p0, nb);
         const int trail = n - p0 - nb;
         const double* Tp = w.T + (long long)p * kNB * kNB;
-        double* YV = Y + (long long)p0 * ldy;
+        double* V = M + p0 + (long long)p0 * ld;
         if (trail > 0) {
-            double* Yt = Y + (long long)(p0 + nb) * ldy;
-            double* Dt = D + p0 + (long long)(p0 + nb) * ldd;
-            // W = Y_V^T Q_Y[:, trail]
-            GemmDesc g1;
-            g1.m = nb; g1.n = trail; g1.k = m; g1.transa = 1;
-            g1.A = YV; g1.lda = ldy; g1.strideA = sy;
-            g1.B = Yt; g1.ldb = ldy; g1.strideB = sy;
+            double* C = M + p0 + (long long)(p0 + nb) * ld;
+            GemmDesc g1;  // W = V^T C
+            g1.m = nb; g1.n = trail; g1.k = L; g1.transa = 1;
+            g1.A = V; g1.lda = ld; g1.strideA = sm;
+            g1.B = C; g1.ldb = ld; g1.strideB = sm;
             g1.C = w.W; g1.ldc = kNB; g1.strideC = (long long)kNB * n;
             g1.batch = batch;
-            if ((e = gemm(g1, st)) != hipSuccess) return e;
-            // Q_D[panel rows, trail] = -T W
-            GemmDesc g2;
+            if ((err = gemm(g1, st)) != hipSuccess) return err;
+            GemmDesc g2;  // W <- T W
             g2.m = nb; g2.n = trail; g2.k = nb;
             g2.A = Tp; g2.lda = kNB; g2.strideA = stT;
             g2.B = w.W; g2.ldb = kNB; g2.strideB = (long long)kNB * n;
-            g2.C = Dt; g2.ldc = ldd; g2.strideC = sd;
-            g2.alpha = -1.0; g2.batch = batch; g2.flags = kAUpper;
-            if ((e = gemm(g2, st)) != hipSuccess) return e;
-            // Q_Y[:, trail] += Y_V Q_D[panel rows, trail]
-            GemmDesc g3;
-            g3.m = m; g3.n = trail; g3.k = nb;
-            g3.A = YV; g3.lda = ldy; g3.strideA = sy;
-            g3.B = Dt; g3.ldb = ldd; g3.strideB = sd;
-            g3.Cin = Yt; g3.ldcin = ldy; g3.strideCin = sy;
-            g3.C = Yt; g3.ldc = ldy; g3.strideC = sy;
-            g3.beta = 1.0; g3.batch = batch;
-            if ((e = gemm(g3, st)) != hipSuccess) return e;
+            g2.C = w.W; g2.ldc = kNB; g2.strideC = (long long)kNB * n;
+            g2.batch = batch; g2.flags = kAUpper;
+            if ((err = gemm(g2, st)) != hipSuccess) return err;
+            GemmDesc g3;  // C -= V W
+            g3.m = L; g3.n = trail; g3.k = nb;
+            g3.A = V; g3.lda = ld; g3.strideA = sm;
+            g3.B = w.W; g3.ldb = kNB; g3.strideB = (long long)kNB * n;
+            g3.Cin = C; g3.ldcin = ld; g3.strideCin = sm;
+            g3.C = C; g3.ldc = ld; g3.strideC = sm;
+            g3.alpha = -1.0; g3.beta = 1.0; g3.batch = batch;
+            if ((err = gemm(g3, st)) != hipSuccess) return err;
         }
-        // Panel columns: Q_D block = I - T, Q_Y[:, panel] = -Y_V T (in place;
-        // one tile column covers all nb <= 64 columns).
-        i_minus_t_kernel<<<batch, 256, 0, st>>>(nb, D + p0 + (long long)p0 * ldd, ldd, sd, Tp, stT);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        GemmDesc g4;
-        g4.m = m; g4.n = nb; g4.k = nb;
-        g4.A = YV; g4.lda = ldy; g4.strideA = sy;
-        g4.B = Tp; g4.ldb = kNB; g4.strideB = stT;
-        g4.C = YV; g4.ldc = ldy; g4.strideC = sy;
-        g4.alpha = -1.0; g4.batch = batch; g4.flags = kBUpper;
-        if ((e = gemm(g4, st)) != hipSuccess) return e;
+        // Panel columns: S = T V_top^T, then Q[rows, panel] = -V S (in place:
+        // one tile column covers the nb <= 64 columns), then +I and zeros above.
+        GemmDesc s;
+        s.m = nb; s.n = nb; s.k = nb; s.transb = 1;
+        s.A = Tp; s.lda = kNB; s.strideA = stT;
+        s.B = V; s.ldb = ld; s.strideB = sm;
+        s.C = w.S; s.ldc = kNB; s.strideC = (long long)kNB * kNB;
+        s.batch = batch; s.flags = kAUpper | kBUpper;
+        if ((err = gemm(s, st)) != hipSuccess) return err;
+        GemmDesc q;
+        q.m = L; q.n = nb; q.k = nb;
+        q.A = V; q.lda = ld; q.strideA = sm;
+        q.B = w.S; q.ldb = kNB; q.strideB = (long long)kNB * kNB;
+        q.C = V; q.ldc = ld; q.strideC = sm;
+        q.alpha = -1.0; q.batch = batch;
+        if ((err = gemm(q, st)) != hipSuccess) return err;
+        const int total = (p0 + nb) * nb;
+        int grid = (total + 255) / 256;
+        if (grid > 1024) grid = 1024;
+        orgqr_fix_kernel<<<dim3(grid, batch), 256, 0, st>>>(p0, nb, M, ld, sm);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
     }
     return hipSuccess;
 }

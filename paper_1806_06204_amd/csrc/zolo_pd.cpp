@@ -71,11 +71,10 @@ Work layout(char* base, int m, int n, int rmax, int panel_coresident) {
     Arena ar{base};
     const size_t mn = (size_t)m * n, nn = (size_t)n * n;
     const int npanels = (n + kPanelNB - 1) / kPanelNB;
-    const int maxG = std::max(1, std::min((m + 63) / 64, std::max(1, panel_coresident)));
     Work w{};
     w.X = ar.take<double>(mn);
     w.Xn = ar.take<double>(mn);
-    w.Y = ar.take<double>(mn * rmax);
+    w.Y = ar.take<double>(((size_t)m + n) * n * rmax);  // stacked [X; sqrt(c) I] per j
     w.D = ar.take<double>(nn * rmax);
     w.G = ar.take<double>(nn);
     w.F = ar.take<double>(nn);
@@ -90,7 +89,10 @@ Work layout(char* base, int m, int n, int rmax, int panel_coresident) {
     w.iflags = ar.take<int>(64);
     w.qr.W = ar.take<double>((size_t)rmax * kPanelNB * n);
     w.qr.T = ar.take<double>((size_t)rmax * npanels * kPanelNB * kPanelNB);
-    w.qr.partials = ar.take<double>((size_t)rmax * 2 * maxG * kPanelNB);
+    w.qr.Rd = ar.take<double>((size_t)rmax * npanels * kPanelNB * kPanelNB);
+    w.qr.S = ar.take<double>((size_t)rmax * kPanelNB * kPanelNB);
+    w.qr.partials = ar.take<double>(std::max(qr_partials_elems(m, n, rmax, panel_coresident),
+                                             qr_partials_elems(m, 0, 1, panel_coresident)));
     w.qr.counters = ar.take<unsigned>((size_t)rmax * npanels);
     w.qr.error_flag = w.iflags + 1;
     w.qr.max_coresident = panel_coresident;
@@ -196,17 +198,17 @@ int qr_step(StepCtx& cx, const Coeffs& co) {
     const Work& w = *cx.w;
     const int m = cx.m, n = cx.n, r = co.r;
     hipStream_t st = cx.h->stream;
-    const long long mn = (long long)m * n, nn = (long long)n * n;
-    HIPCHECK(broadcast_copy(m, n, w.X, m, w.Y, m, mn, r, st));
-    HIPCHECK(hipMemsetAsync(w.D, 0, sizeof(double) * nn * r, st));
+    const long long ld = (long long)m + n, sm = ld * n;
     double piv[kMaxInlineAlpha];
     for (int j = 0; j < r; ++j) piv[j] = std::sqrt(co.c[2 * j]);
-    HIPCHECK(structured_geqrf(m, n, w.Y, m, mn, w.D, n, nn, piv, r, w.qr, st));
-    HIPCHECK(structured_orgqr(m, n, w.Y, m, mn, w.D, n, nn, r, w.qr, st));
+    HIPCHECK(stack_init(m, n, w.X, m, w.Y, ld, sm, piv, r, st));
+    HIPCHECK(structured_geqrf(m, n, n, w.Y, ld, sm, r, w.qr, st));
+    HIPCHECK(structured_orgqr(m, n, n, w.Y, ld, sm, r, w.qr, st));
+    // X_new = Mhat X + sum_j (Mhat a_j / sqrt(c_{2j-1})) Q_{j1} Q_{j2}^T; Q_{j2} is upper triangular.
     GemmDesc g;
     g.m = m; g.n = n; g.k = n; g.transb = 1;
-    g.A = w.Y; g.lda = m; g.strideA = mn;
-    g.B = w.D; g.ldb = n; g.strideB = nn;
+    g.A = w.Y; g.lda = ld; g.strideA = sm;
+    g.B = w.Y + m; g.ldb = ld; g.strideB = sm;
     g.Cin = w.X; g.ldcin = m; g.beta = co.mhat;
     g.C = w.Xn; g.ldc = m;
     g.alpha = co.mhat; g.batch = r; g.reduce = 1; g.nalpha = r;
@@ -363,12 +365,11 @@ int zolo_pd(zolo_handle h, int m, int n, const double* A, int lda, double alpha,
 
     // Step 2: l, a lower bound on sigma_min(X0).
     if (!(l > 0.0)) {
-        // X0 = Q R via the structured QR with a zero identity block, then
+        // X0 = Q R (Householder, no identity block), then
         // l = 1 / (sqrt(n) ||R^{-1}||_1) <= 1 / ||R^{-1}||_2 = sigma_min(X0).
         HIPCHECK(hipMemcpyAsync(w.Y, w.X, sizeof(double) * mn, hipMemcpyDeviceToDevice, st));
-        HIPCHECK(hipMemsetAsync(w.D, 0, sizeof(double) * n * (size_t)n, st));
-        double zero = 0.0;
-        HIPCHECK(structured_geqrf(m, n, w.Y, m, mn, w.D, n, (long long)n * n, &zero, 1, w.qr, st));
+        HIPCHECK(structured_geqrf(m, 0, n, w.Y, m, mn, 1, w.qr, st));
+        HIPCHECK(assemble_r(n, w.Y, m, mn, 1, w.qr, w.D, n, (long long)n * n, st));
         HIPCHECK(trtri_batched(n, w.D, n, (long long)n * n, w.G, n, (long long)n * n, 1, w.trtri,
                                (long long)n * n / 2 + 64 * 64, st));
         HIPCHECK(norm1_upper(n, w.G, n, w.vec_u, w.scal, st));

@@ -78,7 +78,7 @@ def load():
     lib.zolo_dpotrf_batched.argtypes = [P, c_int, P, c_int, c_longlong, c_int, ctypes.POINTER(c_int)]
     lib.zolo_dtrtri_batched.argtypes = [P, c_int, P, c_int, c_longlong, P, c_int, c_longlong, c_int]
     lib.zolo_structured_qr_batched.argtypes = [P, c_int, c_int, D, P, c_int, c_longlong, P, c_int, c_longlong,
-                                               c_int, c_int]
+                                               c_int, c_int]  # M, ldm, strideM, R, ldr, strideR, batch, form_q
     for name in EXPORTS:
         if name not in ("zolo_default_opts",):
             getattr(lib, name).restype = c_int
@@ -253,16 +253,19 @@ class Zolo:
             _raise(rc, "zolo_dtrtri_batched")
         return Ib.transpose(-1, -2)
 
-    def structured_qr(self, Y, pivots, form_q=True):
-        """QR of [p_b I; Y_b] for a (batch, m, n) stack.  Returns (top, bottom):
-        form_q: (Q_D, Q_Y); else (R, Householder Y-parts)."""
+    def structured_qr(self, Y, pivots=None, form_q=True):
+        """QR of [Y_b; p_b I] (pivots given) or of Y_b (pivots None) for a
+        (batch, m, n) stack.  Returns (Q or Householder vectors, R): Q is
+        (batch, m + n, n) ((batch, m, n) without pivots)."""
         torch = _torch()
-        Yb = self._stack_cm(Y)
         batch, m, n = Y.shape
-        Db = torch.empty((batch, n, n), dtype=torch.float64, device=Y.device)
-        piv = (c_double * batch)(*[float(p) for p in pivots])
-        rc = self.lib.zolo_structured_qr_batched(self.h, m, n, piv, c_void_p(Yb.data_ptr()), m, m * n,
-                                                 c_void_p(Db.data_ptr()), n, n * n, batch, int(form_q))
+        e = n if pivots is not None else 0
+        Mb = torch.zeros((batch, n, m + e), dtype=torch.float64, device=Y.device)
+        Mb[:, :, :m] = Y.transpose(-1, -2)
+        Rb = torch.empty((batch, n, n), dtype=torch.float64, device=Y.device)
+        piv = (c_double * batch)(*[float(p) for p in pivots]) if pivots is not None else None
+        rc = self.lib.zolo_structured_qr_batched(self.h, m, n, piv, c_void_p(Mb.data_ptr()), m + e, (m + e) * n,
+                                                 c_void_p(Rb.data_ptr()), n, n * n, batch, int(form_q))
         if rc:
             _raise(rc, "zolo_structured_qr_batched")
-        return Db.transpose(-1, -2), Yb.transpose(-1, -2)
+        return Mb.transpose(-1, -2), Rb.transpose(-1, -2)

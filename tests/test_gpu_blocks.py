@@ -99,23 +99,37 @@ def test_trtri(z, n):
 
 @pytest.mark.parametrize("m,n", [(40, 7), (300, 150), (129, 129), (200, 65)])
 def test_structured_qr(z, m, n):
+    # eq. (12) / Section 3.1: QR of the stacked [Y; p I] with m + 64 live rows per panel.
     rng = np.random.default_rng(m + n)
-    pivots = [0.3, 1.0, 0.0, 1e-3][: 3]
+    pivots = [0.3, 1.0, 1e-3]
     Y = rng.standard_normal((len(pivots), m, n))
-    Rg, _ = z.structured_qr(dev(Y), pivots, form_q=False)
-    QD, QY = z.structured_qr(dev(Y), pivots, form_q=True)
-    Rg, QD, QY = Rg.cpu().numpy(), QD.cpu().numpy(), QY.cpu().numpy()
+    V, Rg = z.structured_qr(dev(Y), pivots, form_q=False)
+    Q, Rq = z.structured_qr(dev(Y), pivots, form_q=True)
+    Rg, Q, Rq = Rg.cpu().numpy(), Q.cpu().numpy(), Rq.cpu().numpy()
+    assert np.array_equal(Rg, Rq)
     for b, p in enumerate(pivots):
-        S = np.vstack([p * np.eye(n), Y[b]])
-        Q = np.vstack([QD[b], QY[b]])
-        assert np.linalg.norm(Q.T @ Q - np.eye(n)) <= 1e-13 * n
-        assert np.linalg.norm(Q @ Rg[b] - S) <= 1e-13 * n * np.linalg.norm(S)
+        S = np.vstack([Y[b], p * np.eye(n)])
+        assert np.linalg.norm(Q[b].T @ Q[b] - np.eye(n)) <= 1e-13 * n
+        assert np.linalg.norm(Q[b] @ Rg[b] - S) <= 1e-13 * n * np.linalg.norm(S)
         assert np.allclose(np.tril(Rg[b], -1), 0.0)
-        assert np.allclose(np.tril(QD[b], -1), 0.0, atol=1e-14)
+        assert np.allclose(np.tril(Q[b][m:], -1), 0.0, atol=1e-14)   # Q_2 upper triangular
         # R agrees with the oracle's Householder QR up to row signs, and the
-        # eq. (12) product Q_top Q_bottom^T is sign independent.
-        Qo, Ro = dense.householder_qr(np.vstack([Y[b], p * np.eye(n)]))
+        # eq. (12) product Q_1 Q_2^T is sign independent.
+        Qo, Ro = dense.householder_qr(S)
         s = np.sign(np.diag(Rg[b])) * np.sign(np.diag(Ro))
         assert np.abs(Rg[b] * s[:, None] - Ro).max() <= 1e-12 * np.abs(Ro).max()
-        if p > 0:
-            assert np.abs(QY[b] @ QD[b].T - Qo[:m] @ Qo[m:].T).max() <= 1e-12
+        assert np.abs(Q[b][:m] @ Q[b][m:].T - Qo[:m] @ Qo[m:].T).max() <= 1e-11
+
+
+@pytest.mark.parametrize("m,n", [(100, 100), (333, 129), (64, 1)])
+def test_plain_qr(z, m, n):
+    rng = np.random.default_rng(3 * m + n)
+    Y = rng.standard_normal((2, m, n))
+    Q, R = z.structured_qr(dev(Y), None, form_q=True)
+    Q, R = Q.cpu().numpy(), R.cpu().numpy()
+    for b in range(2):
+        assert np.linalg.norm(Q[b].T @ Q[b] - np.eye(n)) <= 1e-13 * n
+        assert np.linalg.norm(Q[b] @ R[b] - Y[b]) <= 1e-13 * n * np.linalg.norm(Y[b])
+        _, Ro = dense.householder_qr(Y[b])
+        s = np.sign(np.diag(R[b])) * np.sign(np.diag(Ro))
+        assert np.abs(R[b] * s[:, None] - Ro).max() <= 1e-12 * np.abs(Ro).max()
