@@ -13,6 +13,7 @@
 //     inv([R11 R12; 0 R22]) = [R11^{-1}, -R11^{-1} R12 R22^{-1}; 0, R22^{-1}],
 // batched over all pairs of a level and all matrices.
 #include "misc.hpp"
+#include "stats.hpp"
 
 namespace zolo {
 namespace {
@@ -113,7 +114,9 @@ hipError_t potrf_batched(int n, double* Z, long long ldz, long long sz, int batc
     if (e != hipSuccess) return e;
     for (int k0 = 0; k0 < n; k0 += kB) {
         const int kb = n - k0 < kB ? n - k0 : kB;
+        StatScope sc("potrf_diag_kernel", st, batch * (double)kb * kb * kb / 3.0);
         potrf_diag_kernel<<<batch, 256, 0, st>>>(k0, kb, Z, ldz, sz, info_dev, work);
+        sc.end();
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const int rest = n - k0 - kb;
         if (rest <= 0) break;

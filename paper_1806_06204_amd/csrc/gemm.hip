@@ -15,6 +15,9 @@
 // ordered in groups of 8 tile-rows and the workgroup ids are remapped so that
 // neighbouring tiles run on the same XCD and reuse its L2.
 #include "common.hpp"
+#include "stats.hpp"
+
+#include <cstdio>
 
 namespace zolo {
 namespace {
@@ -164,10 +167,19 @@ template <int BM, int BN>
 hipError_t launch_bm_bn(const GemmDesc& d, hipStream_t s) {
     const int tiles = ((d.m + BM - 1) / BM) * ((d.n + BN - 1) / BN);
     dim3 grid(tiles, d.reduce ? 1 : d.batch, d.batch2);
-    if (!d.transa && !d.transb) dgemm_kernel<BM, BN, false, false><<<grid, 256, 0, s>>>(d);
-    else if (!d.transa && d.transb) dgemm_kernel<BM, BN, false, true><<<grid, 256, 0, s>>>(d);
-    else if (d.transa && !d.transb) dgemm_kernel<BM, BN, true, false><<<grid, 256, 0, s>>>(d);
+    const int which = (d.transa ? 2 : 0) + (d.transb ? 1 : 0);
+    char name[64];
+    if (stats_on()) {
+        snprintf(name, sizeof(name), "dgemm_kernel<%d,%d,%c,%c>", BM, BN, d.transa ? 'T' : 'N', d.transb ? 'T' : 'N');
+    } else {
+        name[0] = 0;
+    }
+    StatScope sc(name, s, gemm_flops(d));
+    if (which == 0) dgemm_kernel<BM, BN, false, false><<<grid, 256, 0, s>>>(d);
+    else if (which == 1) dgemm_kernel<BM, BN, false, true><<<grid, 256, 0, s>>>(d);
+    else if (which == 2) dgemm_kernel<BM, BN, true, false><<<grid, 256, 0, s>>>(d);
     else dgemm_kernel<BM, BN, true, true><<<grid, 256, 0, s>>>(d);
+    sc.end();
     return hipGetLastError();
 }
 

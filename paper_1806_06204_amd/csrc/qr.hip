@@ -27,6 +27,7 @@
 // rows:  W = V^T C,  W <- T^T W,  C -= V W  (ORGQR: T instead of T^T, panels
 // last to first, then the panel's own columns = [I; 0] - V (T V_top^T)).
 #include "misc.hpp"
+#include "stats.hpp"
 
 namespace zolo {
 namespace {
@@ -313,7 +314,9 @@ hipError_t structured_geqrf(int m, int e, int n, double* M, long long ld, long l
         pa.error_flag = w.error_flag;
         pa.spin_limit = 1u << 22;
         void* args[] = {&pa};
+        StatScope sc("panel_kernel", st, 4.0 * L * (double)nb * nb * batch);
         err = hipLaunchCooperativeKernel((const void*)panel_kernel, dim3(pa.G * batch), dim3(kPT), args, 0, st);
+        sc.end();
         if (err != hipSuccess) return err;
         const int trail = n - p0 - nb;
         if (trail <= 0) continue;

@@ -49,7 +49,8 @@ _lib = None
 
 EXPORTS = ["zolo_default_opts", "zolo_create", "zolo_set_stream", "zolo_destroy", "zolo_coeffs", "zolo_pd",
            "zolo_svd", "zolo_dgemm", "zolo_dpotrf_batched", "zolo_dtrtri_batched",
-           "zolo_structured_qr_batched"]
+           "zolo_structured_qr_batched", "zolo_stats_enable", "zolo_stats_reset", "zolo_stats_get",
+           "zolo_stats_count"]
 
 
 def load():
@@ -79,6 +80,10 @@ def load():
     lib.zolo_dtrtri_batched.argtypes = [P, c_int, P, c_int, c_longlong, P, c_int, c_longlong, c_int]
     lib.zolo_structured_qr_batched.argtypes = [P, c_int, c_int, D, P, c_int, c_longlong, P, c_int, c_longlong,
                                                c_int, c_int]  # M, ldm, strideM, R, ldr, strideR, batch, form_q
+    lib.zolo_stats_enable.argtypes = [c_int]
+    lib.zolo_stats_reset.argtypes = []
+    lib.zolo_stats_count.argtypes = []
+    lib.zolo_stats_get.argtypes = [c_int, ctypes.c_char_p, c_int, ctypes.POINTER(c_longlong), D, D]
     for name in EXPORTS:
         if name not in ("zolo_default_opts",):
             getattr(lib, name).restype = c_int
@@ -97,6 +102,28 @@ def coeffs(l, r):
     if rc != 0:
         raise ValueError(f"zolo_coeffs rejected l={l}, r={r} (code {rc})")
     return {"c": list(c), "a": list(a), "mhat": mh.value, "l_next": ln.value}
+
+
+def stats_enable(on=True):
+    load().zolo_stats_enable(int(on))
+
+
+def stats_reset():
+    load().zolo_stats_reset()
+
+
+def stats():
+    """Per-kernel launch statistics: {name: (launches, ms, flops)}."""
+    lib = load()
+    out = {}
+    for i in range(lib.zolo_stats_count()):
+        name = ctypes.create_string_buffer(128)
+        n = c_longlong()
+        ms = c_double()
+        fl = c_double()
+        if lib.zolo_stats_get(i, name, 128, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl)) == 0:
+            out[name.value.decode()] = (n.value, ms.value, fl.value)
+    return out
 
 
 def _torch():

@@ -134,6 +134,6 @@ def test_svd(z):
     Uc, S, Vc, info = z.svd(dev(A), alpha=1.0, l=1e-6, r=4)
     Uc, Vc = Uc.cpu().numpy(), Vc.cpu().numpy()
     assert info["status"] == 0
-    assert np.allclose(S, s, rtol=1e-10, atol=1e-15)
+    assert np.allclose(S, s, rtol=1e-10, atol=1e-14)   # eigenvalues: absolute error ~ eps ||H||
     assert oz.svd_residual_paper(A, Uc, S, Vc) <= 1e-13
-    assert oz.orth_paper(Uc) <= 1e-15 and oz.orth_paper(Vc) <= 1e-15
+    assert oz.orth_paper(Uc) <= 1e-14 and oz.orth_paper(Vc) <= 1e-14

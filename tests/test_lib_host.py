@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def declared_functions():
     names = []
-    for h in ("zolo.h", "zolo_blocks.h"):
+    for h in ("zolo.h", "zolo_blocks.h", "zolo_stats.h"):
         txt = open(os.path.join(ROOT, "include", h)).read()
         names += re.findall(r"^\s*(?:int|void)\s+(zolo_\w+)\s*\(", txt, flags=re.M)
     return names
