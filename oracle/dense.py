@@ -118,7 +118,9 @@ def jacobi_eigh(S, tol=1e-15, max_sweeps=60):
     V = np.eye(n)
     scale = np.linalg.norm(A)  # Frobenius norm (a plain sum of squares)
     for _ in range(max_sweeps):
-        off = np.sqrt(max(0.0, float(np.sum(A * A) - np.sum(np.diag(A) ** 2))))
+        # Off-diagonal mass summed directly: ||A||^2 - ||diag A||^2 would cancel
+        # to zero long before the rotations have converged.
+        off = np.sqrt(float(np.sum((A - np.diag(np.diag(A))) ** 2)))
         if off <= tol * scale:
             break
         for p in range(n - 1):
