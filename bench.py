@@ -68,7 +68,7 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--kappa", type=float, default=1e16)
     ap.add_argument("--r", type=int, default=8)
-    ap.add_argument("--cpu-sample", type=int, default=384)
+    ap.add_argument("--cpu-sample", type=int, default=640)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
