@@ -32,8 +32,8 @@ __global__ __launch_bounds__(256, (BM * BN >= 128 * 128) ? 1 : 2) void dgemm_ker
     constexpr int BK = kBK;
     constexpr int FM = BM / 32, FN = BN / 32;
     constexpr int APT = BM * BK / 256, BPT = BN * BK / 256;
-    __shared__ double As[BK][BM + kPad];
-    __shared__ double Bs[BK][BN + kPad];
+    __shared__ double As[2][BK][BM + kPad];
+    __shared__ double Bs[2][BK][BN + kPad];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave & 1) * (BM / 2), wn = (wave >> 1) * (BN / 2);
@@ -55,6 +55,10 @@ __global__ __launch_bounds__(256, (BM * BN >= 128 * 128) ? 1 : 2) void dgemm_ker
     if (fl & kBLower) kb = max(kb, col0);
     if (fl & kALower) ke = min(ke, row0 + BM);
     if (fl & kBUpper) ke = min(ke, col0 + BN);
+    const int nk = ke > kb ? (ke - kb + BK - 1) / BK : 0;
+    const int nbatch = d.reduce ? d.batch : 1;
+    const int bfirst = d.reduce ? 0 : blockIdx.y;
+    const int ntiles = nk * nbatch;   // (batch, k) slices walked as one sequence
 
     d4 acc[FM][FN];
 #pragma unroll
@@ -62,80 +66,95 @@ __global__ __launch_bounds__(256, (BM * BN >= 128 * 128) ? 1 : 2) void dgemm_ker
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-    const int nbatch = d.reduce ? d.batch : 1;
-    const int bfirst = d.reduce ? 0 : blockIdx.y;
+    // Staging registers: raw loaded values, their validity bits and the
+    // batch multiplier; masking and scaling happen at the LDS store so that
+    // nothing consumes a load before the MFMAs of the current slice.
     double ra[APT], rb[BPT];
-
-    for (int bi = 0; bi < nbatch; ++bi) {
+    unsigned amask = 0, bmask = 0;
+    double al_cur = 1.0;
+    // Loads are unconditional from a clamped (always valid) address and then
+    // masked with a select, so no branch separates them from the MFMAs.
+    auto gload = [&](int t) {
+        const int bi = t / nk;
+        const int k0 = kb + (t - bi * nk) * BK;
         const int b = bfirst + bi;
         const double* __restrict__ A = d.A + (long long)b * d.strideA + (long long)blockIdx.z * d.strideA2;
         const double* __restrict__ B = d.B + (long long)b * d.strideB + (long long)blockIdx.z * d.strideB2;
-        const double al = d.nalpha > 0 ? d.alphas[b] : 1.0;
+        al_cur = d.nalpha > 0 ? d.alphas[b] : 1.0;
+        amask = 0;
+        bmask = 0;
+#pragma unroll
+        for (int s = 0; s < APT; ++s) {
+            const int e = tid + 256 * s;
+            const int i = TA ? e / BK : e % BM;
+            const int kk = TA ? e % BK : e / BM;
+            const int gi = row0 + i, gk = k0 + kk;
+            bool ok = gi < d.m && gk < ke;
+            if (fl & kAUpper) ok = ok && gk >= gi;
+            if (fl & kALower) ok = ok && gk <= gi;
+            const long long off = TA ? gk + (long long)gi * d.lda : gi + (long long)gk * d.lda;
+            ra[s] = A[ok ? off : 0];
+            amask |= ok ? (1u << s) : 0u;
+        }
+#pragma unroll
+        for (int s = 0; s < BPT; ++s) {
+            const int e = tid + 256 * s;
+            const int j = TB ? e % BN : e / BK;
+            const int kk = TB ? e / BN : e % BK;
+            const int gj = col0 + j, gk = k0 + kk;
+            bool ok = gj < d.n && gk < ke;
+            if (fl & kBUpper) ok = ok && gk <= gj;
+            if (fl & kBLower) ok = ok && gk >= gj;
+            const long long off = TB ? gj + (long long)gk * d.ldb : gk + (long long)gj * d.ldb;
+            rb[s] = B[ok ? off : 0];
+            bmask |= ok ? (1u << s) : 0u;
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int s = 0; s < APT; ++s) {
+            const int e = tid + 256 * s;
+            const int i = TA ? e / BK : e % BM;
+            const int kk = TA ? e % BK : e / BM;
+            As[buf][kk][i] = (amask >> s) & 1u ? ra[s] * al_cur : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < BPT; ++s) {
+            const int e = tid + 256 * s;
+            const int j = TB ? e % BN : e / BK;
+            const int kk = TB ? e / BN : e % BK;
+            Bs[buf][kk][j] = (bmask >> s) & 1u ? rb[s] : 0.0;
+        }
+    };
 
-        auto gload = [&](int k0) {
-#pragma unroll
-            for (int s = 0; s < APT; ++s) {
-                const int e = tid + 256 * s;
-                const int i = TA ? e / BK : e % BM;
-                const int kk = TA ? e % BK : e / BM;
-                const int gi = row0 + i, gk = k0 + kk;
-                bool ok = gi < d.m && gk < ke;
-                if (fl & kAUpper) ok = ok && gk >= gi;
-                if (fl & kALower) ok = ok && gk <= gi;
-                double v = 0.0;
-                if (ok) v = TA ? A[gk + (long long)gi * d.lda] : A[gi + (long long)gk * d.lda];
-                ra[s] = v * al;
-            }
-#pragma unroll
-            for (int s = 0; s < BPT; ++s) {
-                const int e = tid + 256 * s;
-                const int j = TB ? e % BN : e / BK;
-                const int kk = TB ? e / BN : e % BK;
-                const int gj = col0 + j, gk = k0 + kk;
-                bool ok = gj < d.n && gk < ke;
-                if (fl & kBUpper) ok = ok && gk <= gj;
-                if (fl & kBLower) ok = ok && gk >= gj;
-                double v = 0.0;
-                if (ok) v = TB ? B[gj + (long long)gk * d.ldb] : B[gk + (long long)gj * d.ldb];
-                rb[s] = v;
-            }
-        };
-        auto lstore = [&]() {
-#pragma unroll
-            for (int s = 0; s < APT; ++s) {
-                const int e = tid + 256 * s;
-                const int i = TA ? e / BK : e % BM;
-                const int kk = TA ? e % BK : e / BM;
-                As[kk][i] = ra[s];
-            }
-#pragma unroll
-            for (int s = 0; s < BPT; ++s) {
-                const int e = tid + 256 * s;
-                const int j = TB ? e % BN : e / BK;
-                const int kk = TB ? e / BN : e % BK;
-                Bs[kk][j] = rb[s];
-            }
-        };
-
-        if (kb >= ke) continue;
-        gload(kb);
-        for (int k0 = kb; k0 < ke; k0 += BK) {
-            __syncthreads();
-            lstore();
-            __syncthreads();
-            if (k0 + BK < ke) gload(k0 + BK);
+    if (ntiles > 0) {
+        gload(0);
+        lstore(0);
+        __syncthreads();
+        if (ntiles > 1) gload(1);
+        for (int t = 0; t < ntiles; ++t) {
+            const int cur = t & 1;
 #pragma unroll
             for (int k4 = 0; k4 < BK; k4 += 4) {
                 double af[FM], bf[FN];
                 const int kr = k4 + (lane >> 4);
 #pragma unroll
-                for (int i = 0; i < FM; ++i) af[i] = As[kr][wm + i * 16 + (lane & 15)];
+                for (int i = 0; i < FM; ++i) af[i] = As[cur][kr][wm + i * 16 + (lane & 15)];
 #pragma unroll
-                for (int j = 0; j < FN; ++j) bf[j] = Bs[kr][wn + j * 16 + (lane & 15)];
+                for (int j = 0; j < FN; ++j) bf[j] = Bs[cur][kr][wn + j * 16 + (lane & 15)];
 #pragma unroll
                 for (int i = 0; i < FM; ++i)
 #pragma unroll
                     for (int j = 0; j < FN; ++j) acc[i][j] = mfma_f64_16x16x4(af[i], bf[j], acc[i][j]);
+            }
+            if (t + 1 < ntiles) {
+                // The other buffer was last read in iteration t-1, before the
+                // barrier that ended it, so it can be refilled now.  Keep the
+                // stores (which wait for the loads in flight) after the MFMAs.
+                __builtin_amdgcn_sched_barrier(0);
+                lstore(cur ^ 1);
+                __syncthreads();
+                if (t + 2 < ntiles) gload(t + 2);
             }
         }
     }

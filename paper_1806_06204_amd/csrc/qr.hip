@@ -107,6 +107,10 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
         __syncthreads();
 
         // Phase B: publish, wait for the other slabs of this matrix, sum in order.
+        // Partials, counter and polls are device-coherent atomics; the
+        // workgroup barrier waits for every partial store to complete before
+        // thread 0 bumps the counter.  No release/acquire fences: those would
+        // write back or invalidate the whole L2 on every column.
         double* part = a.partials + (((long long)b * 2 + (k & 1)) * a.G + g) * (2 * kNB);
         if (tid < nb) {
             __hip_atomic_store(&part[tid], s_w[tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -114,10 +118,10 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
         }
         __syncthreads();
         if (tid == 0) {
-            __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const unsigned target = (unsigned)(k + 1) * (unsigned)a.G;
             unsigned spins = 0;
-            while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
                 if (++spins > a.spin_limit) {
                     atomicOr(a.error_flag, 1);
                     break;
@@ -312,7 +316,7 @@ hipError_t structured_geqrf(int m, int e, int n, double* M, long long ld, long l
         pa.partials = w.partials;
         pa.counters = w.counters + (long long)p * batch;
         pa.error_flag = w.error_flag;
-        pa.spin_limit = 1u << 22;
+        pa.spin_limit = 1u << 24;
         void* args[] = {&pa};
         StatScope sc("panel_kernel", st, 4.0 * L * (double)nb * nb * batch);
         err = hipLaunchCooperativeKernel((const void*)panel_kernel, dim3(pa.G * batch), dim3(kPT), args, 0, st);

@@ -331,6 +331,12 @@ int zolo_pd(zolo_handle h, int m, int n, const double* A, int lda, double alpha,
     hipStream_t st = h->stream;
     const long long mn = (long long)m * n;
     int* hi = reinterpret_cast<int*>(h->host);
+    // Stage times: drain the stream first so queued work is charged to the
+    // stage that queued it.
+    auto lap = [&]() {
+        (void)hipStreamSynchronize(st);
+        return stage.lap();
+    };
     auto finish = [&](int status) {
         inf.status = status;
         inf.t_stage[7] = whole.lap();
@@ -384,7 +390,7 @@ int zolo_pd(zolo_handle h, int m, int n, const double* A, int lda, double alpha,
     // Step 3: r.
     if (r < 1) r = choose_r(l);
     inf.r_used = r;
-    inf.t_stage[0] += stage.lap();
+    inf.t_stage[0] += lap();
 
     StepCtx cx{h, &w, m, n};
     bool g_valid = false;   // G holds X^T X of the current X
@@ -402,13 +408,13 @@ int zolo_pd(zolo_handle h, int m, int n, const double* A, int lda, double alpha,
             } else if (rc) {
                 return finish(rc);
             }
-            inf.t_stage[2] += stage.lap();
+            inf.t_stage[2] += lap();
         }
         if (kind == 'Q') {
             if ((rc = qr_step(cx, co))) return finish(rc);
             if ((rc = readback(h, w.iflags + 1, sizeof(int)))) return finish(rc);
             if (hi[0]) return finish(ZOLO_KERNEL);
-            inf.t_stage[1] += stage.lap();
+            inf.t_stage[1] += lap();
         }
         g_valid = false;
         inf.kind[it] = kind;
@@ -422,7 +428,7 @@ int zolo_pd(zolo_handle h, int m, int n, const double* A, int lda, double alpha,
             if ((rc = readback(h, w.scal, 2 * sizeof(double)))) return finish(rc);
             const double rel = std::sqrt(h->host[0]) / std::sqrt(h->host[1]);
             l = l_pred;
-            inf.t_stage[3] += stage.lap();
+            inf.t_stage[3] += lap();
             if (rel <= std::pow(kEps, 1.0 / (2 * r + 1))) {
                 status = 0;
                 break;
@@ -438,7 +444,7 @@ int zolo_pd(zolo_handle h, int m, int n, const double* A, int lda, double alpha,
                 g_valid = true;
                 const double d = std::sqrt(std::max(h->host[0], 0.0)) / std::sqrt((double)n);
                 inf.orth_check = d;
-                inf.t_stage[3] += stage.lap();
+                inf.t_stage[3] += lap();
                 if (d <= opts.tau) {
                     status = 0;
                     break;
@@ -464,7 +470,7 @@ int zolo_pd(zolo_handle h, int m, int n, const double* A, int lda, double alpha,
     cx.flops_exec += 2.0 * m * (double)n * n;
     inf.flops_paper += 2.0 * m * (double)n * n;
     HIPCHECK(hipStreamSynchronize(st));
-    inf.t_stage[4] += stage.lap();
+    inf.t_stage[4] += lap();
 
     if (opts.compute_errors) {
         GemmDesc pg;  // Xn = Qp H
