@@ -62,7 +62,7 @@ struct QrWork {
 
 // Doubles each QrWork array needs for m x n, `batch` matrices, e extra rows.
 inline size_t qr_partials_elems(int m, int e, int batch, int max_coresident) {
-    int G = (m + e + 255) / 256;
+    int G = (m + e + 63) / 64;  // the most workgroups any row target can ask for
     int cap = max_coresident / (batch > 0 ? batch : 1);
     if (cap < 1) cap = 1;
     if (G > cap) G = cap;

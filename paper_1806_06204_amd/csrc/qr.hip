@@ -29,6 +29,9 @@
 #include "misc.hpp"
 #include "stats.hpp"
 
+#include <cstdlib>
+#include <map>
+
 namespace zolo {
 namespace {
 
@@ -45,10 +48,15 @@ struct PanelArgs {
     unsigned* counters;                  // [batch]
     int* error_flag;
     unsigned spin_limit;
+    int lds_stride;                      // InLds: leading dimension of the slab in LDS
 };
 
+// The workgroup's slab (rows [r0, r1) of the panel) lives either in LDS
+// (InLds: loaded once, written back at the end) or stays in global memory.
+// Row r of the slab, column j, is X[(r - r0) + j * xld] with X = LDS or P + r0.
+template <bool InLds>
 __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
-    __shared__ double sT[kNB][kNB + 1];
+    extern __shared__ double smem[];
     __shared__ double s_d[kNB], s_pr[kNB], s_coef[kNB], s_z[kNB], s_w[2 * kNB];
     const int g = blockIdx.x % a.G, b = blockIdx.x / a.G;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -57,7 +65,19 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
     const int r0 = g * a.rows_per_wg;
     const int r1 = min(a.L, r0 + a.rows_per_wg);
     const int nb = a.nb;
-    for (int e = tid; e < kNB * kNB; e += kPT) sT[e / kNB][e % kNB] = 0.0;
+    const long long xld = InLds ? a.lds_stride : ld;
+    double* __restrict__ X = InLds ? smem : P + r0;
+    if (InLds) {
+        for (int e = tid; e < (r1 - r0) * nb; e += kPT) {
+            const int rl = e % (r1 - r0), j = e / (r1 - r0);
+            X[rl + j * xld] = P[(r0 + rl) + j * ld];
+        }
+    }
+    // Thread i < kNB keeps row i of T in registers (indexed only by unrolled
+    // loops, so it never leaves the register file).
+    double Trow[kNB];
+#pragma unroll
+    for (int l = 0; l < kNB; ++l) Trow[l] = 0.0;
     if (tid < kNB) s_coef[tid] = 0.0;
     __syncthreads();
     unsigned* ctr = a.counters + b;
@@ -71,37 +91,42 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
         const double ck = k > 0 ? s_coef[k] : 0.0;
         const int lo = max(r0, k > 0 ? k - 1 : 0);
         for (int row = lo + lane; row < r1; row += 64) {
-            const double vprev = k > 0 ? (row == k - 1 ? 1.0 : P[row + (k - 1) * ld]) : 0.0;
-            const double xk = P[row + k * ld] - ck * vprev;
+            const int rl = row - r0;
+            // All loads of the row first, then arithmetic, then stores.
+            double val[kColsPerWave];
+#pragma unroll
+            for (int q = 0; q < kColsPerWave; ++q) {
+                const int i = min(wave + 4 * q, nb - 1);
+                val[q] = X[rl + i * xld];
+            }
+            const double vraw = k > 0 ? X[rl + (k - 1) * xld] : 0.0;
+            const double xraw = X[rl + k * xld];
+            const double vprev = k > 0 ? (row == k - 1 ? 1.0 : vraw) : 0.0;
+            const double xk = xraw - ck * vprev;
 #pragma unroll
             for (int q = 0; q < kColsPerWave; ++q) {
                 const int i = wave + 4 * q;
+                if (i > k && k > 0) val[q] -= s_coef[min(i, kNB - 1)] * vprev;
+                if (i == k) val[q] = xk;
                 if (i < nb) {
-                    double val;
-                    if (i < k) {
-                        val = P[row + i * ld];
-                    } else if (i == k) {
-                        val = xk;
-                    } else {
-                        val = P[row + i * ld];
-                        if (k > 0) {
-                            val -= s_coef[i] * vprev;
-                            P[row + i * ld] = val;
-                        }
-                    }
-                    if (row > k) acc[q] += xk * val;
-                    else if (row == k) prv[q] = val;
+                    if (row > k) acc[q] += xk * val[q];
+                    else if (row == k) prv[q] = val[q];
                 }
+            }
+#pragma unroll
+            for (int q = 0; q < kColsPerWave; ++q) {
+                const int i = wave + 4 * q;
+                if (i > k && k > 0 && i < nb) X[rl + i * xld] = val[q];
             }
         }
 #pragma unroll
         for (int q = 0; q < kColsPerWave; ++q) {
-            const double s = wave_sum(acc[q]);
-            const double p = wave_sum(prv[q]);   // only the lane holding the pivot row is nonzero
+            const double sa = wave_sum(acc[q]);
+            const double sp = wave_sum(prv[q]);   // only the lane holding the pivot row is nonzero
             const int i = wave + 4 * q;
             if (lane == 0 && i < nb) {
-                s_w[i] = s;
-                s_w[kNB + i] = p;
+                s_w[i] = sa;
+                s_w[kNB + i] = sp;
             }
         }
         __syncthreads();
@@ -131,13 +156,25 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
         }
         __syncthreads();
         if (tid < 2 * nb) {
+            // Coherent loads have memory latency: issue them eight at a time
+            // and add in a fixed order.
             const int idx = tid < nb ? tid : kNB + (tid - nb);
             const double* pb = a.partials + ((long long)b * 2 + (k & 1)) * a.G * (2 * kNB);
-            double s = 0.0;
-            for (int gg = 0; gg < a.G; ++gg)
-                s += __hip_atomic_load(&pb[gg * (2 * kNB) + idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (tid < nb) s_d[tid] = s;
-            else s_pr[tid - nb] = s;
+            double sum = 0.0;
+            int gg = 0;
+            for (; gg + 8 <= a.G; gg += 8) {
+                double v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    v[u] = __hip_atomic_load(&pb[(gg + u) * (2 * kNB) + idx], __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) sum += v[u];
+            }
+            for (; gg < a.G; ++gg)
+                sum += __hip_atomic_load(&pb[gg * (2 * kNB) + idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (tid < nb) s_d[tid] = sum;
+            else s_pr[tid - nb] = sum;
         }
         __syncthreads();
 
@@ -161,17 +198,27 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
             if (tid < k) s_z[tid] = w;
         }
         __syncthreads();
+        // T[0:k, k] = -tau T[0:k, 0:k] z;  T[k][k] = tau.
         if (tid < k) {
-            double s = 0.0;
-            for (int l = tid; l < k; ++l) s += sT[tid][l] * s_z[l];
-            sT[tid][k] = -tau * s;
+            double sum = 0.0;
+#pragma unroll
+            for (int l = 0; l < kNB; ++l)
+                if (l >= tid && l < k) sum += Trow[l] * s_z[l];
+            const double tv = -tau * sum;
+#pragma unroll
+            for (int l = 0; l < kNB; ++l)
+                if (l == k) Trow[l] = tv;
+        } else if (tid == k) {
+#pragma unroll
+            for (int l = 0; l < kNB; ++l)
+                if (l == k) Trow[l] = tau;
         }
-        if (tid == 0) sT[k][k] = tau;
         // Phase D: column k: R entry on row k-1, beta on the pivot, v below.
         for (int row = max(r0, k > 0 ? k - 1 : 0) + tid; row < r1; row += kPT) {
-            const double vprev = k > 0 ? (row == k - 1 ? 1.0 : P[row + (k - 1) * ld]) : 0.0;
-            const double x = P[row + k * ld] - ck * vprev;
-            P[row + k * ld] = row == k ? beta : (row > k ? scale * x : x);
+            const int rl = row - r0;
+            const double vprev = k > 0 ? (row == k - 1 ? 1.0 : X[rl + (k - 1) * xld]) : 0.0;
+            const double x = X[rl + k * xld] - ck * vprev;
+            X[rl + k * xld] = row == k ? beta : (row > k ? scale * x : x);
         }
         __syncthreads();
     }
@@ -182,14 +229,22 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
         const int i = e % kNB, j = e / kNB;
         if ((i >= r0 && i < r1) || (g == 0 && i >= a.L)) {
             const bool in = i < nb && j < nb && i < a.L;
-            const double v = in ? P[i + j * ld] : 0.0;
+            const double v = in ? X[(i - r0) + j * xld] : 0.0;
             Rd[e] = (in && i <= j) ? v : 0.0;
-            if (in && i <= j) P[i + j * ld] = (i == j) ? 1.0 : 0.0;
+            if (in && i <= j) X[(i - r0) + j * xld] = (i == j) ? 1.0 : 0.0;
         }
     }
-    if (g == 0) {
+    if (InLds) {
+        __syncthreads();
+        for (int e = tid; e < (r1 - r0) * nb; e += kPT) {
+            const int rl = e % (r1 - r0), j = e / (r1 - r0);
+            P[(r0 + rl) + j * ld] = X[rl + j * xld];
+        }
+    }
+    if (g == 0 && tid < kNB) {
         double* Tb = a.T + b * a.st;
-        for (int e = tid; e < kNB * kNB; e += kPT) Tb[e] = sT[e % kNB][e / kNB];
+#pragma unroll
+        for (int l = 0; l < kNB; ++l) Tb[tid + l * kNB] = Trow[l];
     }
 }
 
@@ -242,11 +297,73 @@ __global__ void assemble_r_kernel(int n, const double* __restrict__ M, long long
 
 struct Geometry {
     int G, rows;
+    bool lds;
 };
 
+// Rows each workgroup owns when the slab stays in global memory
+// (ZOLO_PANEL_ROWS overrides; default 256).
+int panel_rows_target() {
+    static int v = [] {
+        const char* e = getenv("ZOLO_PANEL_ROWS");
+        int x = e ? atoi(e) : 0;
+        return x >= 64 && x <= 8192 ? x : 256;
+    }();
+    return v;
+}
+
+constexpr int kStaticLds = 6 * kNB * 8 + 256;
+
+int lds_limit() {
+    static int v = [] {
+        int dev = 0, bytes = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return 0;
+        if (hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 0;
+        if (hipFuncSetAttribute((const void*)panel_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                bytes - kStaticLds) != hipSuccess)
+            return 0;
+        return bytes;
+    }();
+    return v;
+}
+
+int cu_count() {
+    static int v = [] {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+        return cus;
+    }();
+    return v;
+}
+
+// Co-resident workgroups of the LDS panel kernel with an R-row slab.
+int lds_coresident(int R) {
+    static std::map<int, int> cache;
+    auto it = cache.find(R);
+    if (it != cache.end()) return it->second;
+    int per_cu = 0;
+    const size_t dyn = (size_t)R * kNB * sizeof(double);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)panel_kernel<true>, kPT, dyn) !=
+        hipSuccess)
+        per_cu = 0;
+    return cache[R] = per_cu * cu_count();
+}
+
 Geometry panel_geometry(int L, int batch, int max_coresident) {
-    // ~256 rows per workgroup, at least 64, every workgroup resident.
-    int G = (L + 255) / 256;
+    // Slab in LDS when every workgroup of the launch can be resident with it.
+    const int limit = lds_limit();
+    if (limit > 0) {
+        const int max_rows = (limit - kStaticLds) / (kNB * (int)sizeof(double));
+        for (int R = 64; R <= max_rows; R += 16) {
+            const int G = (L + R - 1) / R;
+            if (G * batch <= lds_coresident(R)) {
+                const int rows = (L + G - 1) / G;
+                return {G, rows, true};
+            }
+        }
+    }
+    const int target = panel_rows_target();
+    int G = (L + target - 1) / target;
     if (G < 1) G = 1;
     int cap = max_coresident / batch;
     if (cap < 1) cap = 1;
@@ -254,7 +371,7 @@ Geometry panel_geometry(int L, int batch, int max_coresident) {
     int rows = (L + G - 1) / G;
     if (rows < 64) rows = 64;
     G = (L + rows - 1) / rows;
-    return {G, rows};
+    return {G, rows, false};
 }
 
 inline int live_rows(int m, int e, int p0, int nb) {
@@ -268,7 +385,8 @@ int panel_max_coresident() {
     int dev = 0, per_cu = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)panel_kernel, kPT, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)panel_kernel<false>, kPT, 0) !=
+        hipSuccess)
         return 0;
     return per_cu * cus;
 }
@@ -317,9 +435,15 @@ hipError_t structured_geqrf(int m, int e, int n, double* M, long long ld, long l
         pa.counters = w.counters + (long long)p * batch;
         pa.error_flag = w.error_flag;
         pa.spin_limit = 1u << 24;
+        pa.lds_stride = geo.rows;
         void* args[] = {&pa};
-        StatScope sc("panel_kernel", st, 4.0 * L * (double)nb * nb * batch);
-        err = hipLaunchCooperativeKernel((const void*)panel_kernel, dim3(pa.G * batch), dim3(kPT), args, 0, st);
+        StatScope sc(geo.lds ? "panel_kernel<lds>" : "panel_kernel<global>", st, 4.0 * L * (double)nb * nb * batch);
+        if (geo.lds)
+            err = hipLaunchCooperativeKernel((const void*)panel_kernel<true>, dim3(pa.G * batch), dim3(kPT), args,
+                                             (size_t)geo.rows * kNB * sizeof(double), st);
+        else
+            err = hipLaunchCooperativeKernel((const void*)panel_kernel<false>, dim3(pa.G * batch), dim3(kPT), args, 0,
+                                             st);
         sc.end();
         if (err != hipSuccess) return err;
         const int trail = n - p0 - nb;

@@ -35,6 +35,19 @@ def dev(x):
     return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
 
 
+def same_schedule(info, io, tau=5e-14):
+    """Step kinds follow from identical host scalars and must agree.  The only
+    rounding-dependent decision is the verified stop ||X^T X - I||_F/sqrt(n) <= tau:
+    when one side needs one more step, the oracle's check must have been
+    within a factor 10 of tau."""
+    g, o = info["kinds"], io["kinds"]
+    k = min(len(g), len(o))
+    assert g[:k] == o[:k]
+    if len(g) != len(o):
+        assert abs(len(g) - len(o)) == 1, (g, o)
+        assert io["orth_checks"] and 0.1 * tau <= io["orth_checks"][0] <= 10 * tau, io["orth_checks"]
+
+
 def run_and_compare(z, A, alpha, l, r, kappa=None, h_tol=1e-12, **opts):
     Qp, H, info = z.pd(dev(A), alpha=alpha, l=l, r=r, compute_errors=1, **opts)
     Qp, H = Qp.cpu().numpy(), H.cpu().numpy()
@@ -50,7 +63,7 @@ def run_and_compare(z, A, alpha, l, r, kappa=None, h_tol=1e-12, **opts):
     print(f"  gpu kinds={''.join(info['kinds'])} oracle={''.join(io['kinds'])} bwd={bwd:.2e} orth={orth:.2e} "
           f"dH={dh:.2e} lib bwd={info['bwd_err']:.2e} orth={info['orth_err']:.2e}", flush=True)
     assert info["status"] == 0
-    assert info["kinds"] == io["kinds"]
+    same_schedule(info, io)
     assert bwd <= BAR and orth <= BAR
     assert abs(info["bwd_err"] - bwd) <= 1e-15 + 0.1 * bwd
     assert dh <= h_tol
