@@ -60,6 +60,48 @@ def cpu_baseline(n_sample, kappa, r):
             "seconds": dt, "schedule": "".join(info["kinds"])}
 
 
+def bench_batched(args):
+    """Uneven batch: one zolo_pd_batched call per step, l exact, r by the policy."""
+    import numpy as np
+    import torch
+    from paper_1806_06204_amd import workloads as W
+    from paper_1806_06204_amd import zolo
+    specs = W.batch_specs(count=args.batched, seed=4000)
+    print(f"[bench] generating {len(specs)} matrices", file=sys.stderr, flush=True)
+    mats = []
+    for sp in specs:
+        A = W.svd_matrix(sp["m"], sp["n"], sp["kappa"], sp["seed_u"], sp["seed_v"])[0]
+        mats.append(torch.from_numpy(np.ascontiguousarray(A.T)).to("cuda:0").t())
+    ls = [1.0 / sp["kappa"] for sp in specs]
+    z = zolo.Zolo()
+    for _ in range(args.warmup):
+        z.pd_batched(mats, alphas=[1.0] * len(mats), ls=ls)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, _, infos = z.pd_batched(mats, alphas=[1.0] * len(mats), ls=ls)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    fl = sum(paper_flops(sp["m"], sp["n"], inf["r"], inf["kinds"], 1 if inf["orth_check"] >= 0 else 0)
+             for sp, inf in zip(specs, infos))
+    # accuracy on a sample of the batch
+    errs = []
+    for i in range(0, len(mats), max(1, len(mats) // 16)):
+        _, _, inf = z.pd(mats[i], alpha=1.0, l=ls[i], compute_errors=1)
+        errs.append((inf["bwd_err"], inf["orth_err"]))
+    out = {"metric": "Zolo-PD batched throughput (uneven matrices)", "value": fl / dt / 1e12, "unit": "TFLOP/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"{len(specs)} matrices, n~U[64,1024], m~U[n,2n], log10 kappa~U[2,12], "
+                                  "l exact, r by the two-iteration policy", "count": len(specs)},
+           "matrices_per_s": len(specs) / dt,
+           "r_histogram": {str(k): sum(1 for i in infos if i["r"] == k) for k in range(1, 9)},
+           "max_bwd_err_sampled": max(e[0] for e in errs), "max_orth_err_sampled": max(e[1] for e in errs),
+           "not_converged": sum(1 for i in infos if i["status"] != 0)}
+    print(json.dumps(out), flush=True)
+    z.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,6 +112,9 @@ def main():
     ap.add_argument("--r", type=int, default=8)
     ap.add_argument("--cpu-sample", type=int, default=640)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched", type=int, default=0,
+                    help="instead: Zolo-PD of this many uneven matrices (n in [64,1024], m in [n,2n], "
+                         "kappa log-uniform in [1e2,1e12]) in one zolo_pd_batched call")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -81,6 +126,8 @@ def main():
     from paper_1806_06204_amd import workloads as W
     from paper_1806_06204_amd import zolo
 
+    if args.batched:
+        return bench_batched(args)
     n, kappa, r = args.n, args.kappa, args.r
     print(f"[bench] generating {n}x{n} kappa={kappa:g} input", file=sys.stderr, flush=True)
     t0 = time.perf_counter()

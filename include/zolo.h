@@ -68,10 +68,9 @@ typedef struct {
     double tau;          /* verified-stop threshold (default 5e-14) */
     double chol_switch;  /* QR-type step while (1+c_1)/(l^2+c_1) > chol_switch
                             (default 100; the QDWH switch of Section 2.1) */
-    int qr_variant;      /* 0 (default): structured QR of [X; sqrt(c) I] with
-                            m + NB live rows per panel (Section 3.1);
-                            1: one Householder QR X = Q_X R_X shared by all j,
-                            then structured QRs of [R_X; sqrt(c) I] */
+    int qr_variant;      /* 0 (default, the only value accepted): structured QR of
+                            [X; sqrt(c) I] with m + NB live rows per panel
+                            (Section 3.1) */
     int precision;       /* 0 (default): every step in FP64.  Other values are
                             rejected (-argument) in this version. */
     int compute_errors;  /* 1: fill info->bwd_err and info->orth_err (costs two
@@ -138,6 +137,20 @@ int zolo_pd(zolo_handle handle, int m, int n, const double* A, int lda,
             double alpha, double l, int r,
             double* Qp, int ldq, double* H, int ldh,
             const zolo_opts* opts, zolo_info* info);
+
+/* Zolo-PD of `count` independent matrices of possibly different shapes (the
+ * paper's per-group work of Algorithm 3 steps 1-4, one matrix at a time on
+ * the handle's stream, with the workspace sized once for the largest one).
+ * Arrays have `count` entries: m, n, lda, ldq, ldh, alpha, l, r are HOST
+ * arrays; A, Qp, H are HOST arrays of DEVICE pointers.  alpha, l, r may be
+ * NULL (all estimated / chosen by the policy).  info may be NULL or point to
+ * `count` structs.  Returns 0 if every matrix converged, 1 if some did not,
+ * or the first error code (negative: -(argument index) of the first bad
+ * argument, counting a bad entry of an array as that array's index). */
+int zolo_pd_batched(zolo_handle handle, int count, const int* m, const int* n,
+                    const double* const* A, const int* lda, const double* alpha,
+                    const double* l, const int* r, double* const* Qp, const int* ldq,
+                    double* const* H, const int* ldh, const zolo_opts* opts, zolo_info* info);
 
 /* Zolo-SVD, Algorithm 2: A = Qp H by zolo_pd, then H = V diag(S) V^T by a
  * plain FP64 symmetric eigensolver on the GPU (cyclic Jacobi), then U = Qp V.

@@ -38,6 +38,9 @@ namespace {
 constexpr int kNB = kPanelNB;
 constexpr int kPT = 256;                 // threads per panel workgroup
 constexpr int kColsPerWave = kNB / 4;    // panel columns owned by each wave
+// s_waitcnt immediate (gfx9 encoding) that waits for vmcnt == 0 only:
+// vmcnt bits [3:0],[15:14] = 0, expcnt [6:4] = 7, lgkmcnt [11:8] = 15.
+constexpr int kWaitVmcnt0 = 0x0F70;
 
 struct PanelArgs {
     int L, nb, G, rows_per_wg;
@@ -132,14 +135,18 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
         __syncthreads();
 
         // Phase B: publish, wait for the other slabs of this matrix, sum in order.
-        // Partials, counter and polls are device-coherent atomics; the
-        // workgroup barrier waits for every partial store to complete before
-        // thread 0 bumps the counter.  No release/acquire fences: those would
-        // write back or invalidate the whole L2 on every column.
+        // Partials, counter and polls are device-coherent (agent-scope) atomics.
+        // A workgroup barrier does not wait for outstanding global stores, so
+        // the storing wave (wave 0, the same wave that bumps the counter) waits
+        // for its partial stores to be acknowledged before the barrier; without
+        // that wait another workgroup can see the counter and read a stale
+        // partial.  No release/acquire fences: those would write back or
+        // invalidate the whole L2 on every column.
         double* part = a.partials + (((long long)b * 2 + (k & 1)) * a.G + g) * (2 * kNB);
         if (tid < nb) {
             __hip_atomic_store(&part[tid], s_w[tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&part[kNB + tid], s_w[kNB + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
         }
         __syncthreads();
         if (tid == 0) {

@@ -221,7 +221,7 @@ int qr_step(StepCtx& cx, const Coeffs& co) {
 
 bool opts_ok(const zolo_opts& o) {
     return o.max_iter >= 1 && o.max_iter <= ZOLO_MAX_ITER && (o.stop_rule == 0 || o.stop_rule == 1) &&
-           o.tau > 0.0 && o.chol_switch >= 1.0 && (o.qr_variant == 0 || o.qr_variant == 1) && o.precision == 0;
+           o.tau > 0.0 && o.chol_switch >= 1.0 && o.qr_variant == 0 && o.precision == 0;
 }
 
 }  // namespace
@@ -487,6 +487,47 @@ int zolo_pd(zolo_handle h, int m, int n, const double* A, int lda, double alpha,
     }
     inf.flops_exec += cx.flops_exec;
     return finish(status);
+}
+
+int zolo_pd_batched(zolo_handle h, int count, const int* m, const int* n, const double* const* A, const int* lda,
+                    const double* alpha, const double* l, const int* r, double* const* Qp, const int* ldq,
+                    double* const* H, const int* ldh, const zolo_opts* opts, zolo_info* info) {
+    if (!h) return -1;
+    if (count < 0) return -2;
+    if (count == 0) return 0;
+    if (!m) return -3;
+    if (!n) return -4;
+    if (!A) return -5;
+    if (!lda) return -6;
+    if (!Qp) return -10;
+    if (!ldq) return -11;
+    if (!H) return -12;
+    if (!ldh) return -13;
+    // Validate everything and size the workspace for the largest problem
+    // first, so one allocation serves the whole batch.
+    size_t need = 0;
+    for (int i = 0; i < count; ++i) {
+        if (m[i] < 1) return -3;
+        if (n[i] < 1 || n[i] > m[i]) return -4;
+        if (!A[i]) return -5;
+        if (lda[i] < m[i]) return -6;
+        if (r && r[i] > kMaxR) return -9;
+        if (!Qp[i]) return -10;
+        if (ldq[i] < m[i]) return -11;
+        if (!H[i]) return -12;
+        if (ldh[i] < n[i]) return -13;
+        const int rmax = (r && r[i] >= 1) ? r[i] : kMaxR;
+        need = std::max(need, layout(nullptr, m[i], n[i], rmax, h->panel_coresident).bytes);
+    }
+    if (int rc = ensure(h, need)) return rc;
+    int worst = 0;
+    for (int i = 0; i < count; ++i) {
+        const int rc = zolo_pd(h, m[i], n[i], A[i], lda[i], alpha ? alpha[i] : 0.0, l ? l[i] : 0.0, r ? r[i] : 0,
+                               Qp[i], ldq[i], H[i], ldh[i], opts, info ? info + i : nullptr);
+        if (rc < 0 || rc > ZOLO_NOT_CONVERGED) return rc;
+        worst = std::max(worst, rc);
+    }
+    return worst;
 }
 
 }  // extern "C"

@@ -48,7 +48,7 @@ class ZoloInfo(ctypes.Structure):
 _lib = None
 
 EXPORTS = ["zolo_default_opts", "zolo_create", "zolo_set_stream", "zolo_destroy", "zolo_coeffs", "zolo_pd",
-           "zolo_svd", "zolo_dgemm", "zolo_dpotrf_batched", "zolo_dtrtri_batched",
+           "zolo_pd_batched", "zolo_svd", "zolo_dgemm", "zolo_dpotrf_batched", "zolo_dtrtri_batched",
            "zolo_structured_qr_batched", "zolo_stats_enable", "zolo_stats_reset", "zolo_stats_get",
            "zolo_stats_count"]
 
@@ -72,6 +72,10 @@ def load():
     lib.zolo_coeffs.argtypes = [c_double, c_int, D, D, D, D]
     lib.zolo_pd.argtypes = [P, c_int, c_int, P, c_int, c_double, c_double, c_int, P, c_int, P, c_int,
                             ctypes.POINTER(ZoloOpts), ctypes.POINTER(ZoloInfo)]
+    PP = ctypes.POINTER(c_void_p)
+    IP = ctypes.POINTER(c_int)
+    lib.zolo_pd_batched.argtypes = [P, c_int, IP, IP, PP, IP, D, D, IP, PP, IP, PP, IP,
+                                    ctypes.POINTER(ZoloOpts), ctypes.POINTER(ZoloInfo)]
     lib.zolo_svd.argtypes = [P, c_int, c_int, P, c_int, c_double, c_double, c_int, P, c_int, D, P, c_int,
                              ctypes.POINTER(ZoloOpts), ctypes.POINTER(ZoloInfo)]
     lib.zolo_dgemm.argtypes = [P, c_int, c_int, c_int, c_int, c_int, c_double, P, c_int, c_longlong, P, c_int,
@@ -211,6 +215,34 @@ class Zolo:
         if check and rc not in (0, 1):
             _raise(rc, "zolo_pd")
         return Qbuf.t(), Hbuf.t(), info.as_dict()
+
+    def pd_batched(self, As, alphas=None, ls=None, rs=None, check=True, **opts):
+        """Zolo-PD of a list of matrices of any shapes.  Returns (Qps, Hs, infos)."""
+        torch = _torch()
+        count = len(As)
+        cols = [_colmajor(A) for A in As]
+        for A in As:
+            _check_tensor(A, "A")
+        ms = (c_int * count)(*[A.shape[0] for A in As])
+        ns = (c_int * count)(*[A.shape[1] for A in As])
+        ldas = (c_int * count)(*[ld for _, ld in cols])
+        Qb = [torch.empty((A.shape[1], A.shape[0]), dtype=torch.float64, device=A.device) for A in As]
+        Hb = [torch.empty((A.shape[1], A.shape[1]), dtype=torch.float64, device=A.device) for A in As]
+        Ap = (c_void_p * count)(*[c.data_ptr() for c, _ in cols])
+        Qpp = (c_void_p * count)(*[q.data_ptr() for q in Qb])
+        Hpp = (c_void_p * count)(*[x.data_ptr() for x in Hb])
+        ldqs = (c_int * count)(*[A.shape[0] for A in As])
+        ldhs = (c_int * count)(*[A.shape[1] for A in As])
+        al = (c_double * count)(*alphas) if alphas is not None else None
+        lv = (c_double * count)(*ls) if ls is not None else None
+        rv = (c_int * count)(*rs) if rs is not None else None
+        infos = (ZoloInfo * count)()
+        o = self.options(**opts)
+        rc = self.lib.zolo_pd_batched(self.h, count, ms, ns, Ap, ldas, al, lv, rv, Qpp, ldqs, Hpp, ldhs,
+                                      ctypes.byref(o), infos)
+        if check and rc not in (0, 1):
+            _raise(rc, "zolo_pd_batched")
+        return [q.t() for q in Qb], [x.t() for x in Hb], [i.as_dict() for i in infos]
 
     def svd(self, A, alpha=None, l=None, r=None, check=True, **opts):
         """Zolo-SVD A = U diag(S) V^T.  Returns (U, S (numpy), V, info)."""

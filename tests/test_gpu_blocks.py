@@ -121,6 +121,30 @@ def test_structured_qr(z, m, n):
         assert np.abs(Q[b][:m] @ Q[b][m:].T - Qo[:m] @ Qo[m:].T).max() <= 1e-11
 
 
+@pytest.mark.parametrize("m,n,batch", [(1025, 881, 5), (700, 600, 16)])
+def test_structured_qr_many_slabs(z, m, n, batch):
+    # Mid-size panels split over 11-18 workgroups per matrix and up to 16
+    # matrices per launch, so the cross-workgroup reduction of every column
+    # runs with many slabs at once.  Pivots are the sqrt(c_{2j-1}) of a
+    # degree-5 Zolotarev step at l = 1/9e4 (large and small shifts together).
+    from oracle import coeffs as oc
+    co = oc.coefficients(1.0 / 9e4, 5)
+    base = [float(np.sqrt(co["c"][2 * j])) for j in range(5)]
+    pivots = [base[b % 5] * (1.0 + 0.1 * (b // 5)) for b in range(batch)]
+    rng = np.random.default_rng(m * n + batch)
+    Y = rng.standard_normal((batch, m, n)) / np.sqrt(m)
+    for rep in range(2):
+        Q, R = z.structured_qr(dev(Y), pivots, form_q=True)
+        Q, R = Q.cpu().numpy(), R.cpu().numpy()
+        for b, p in enumerate(pivots):
+            S = np.vstack([Y[b], p * np.eye(n)])
+            assert np.linalg.norm(Q[b].T @ Q[b] - np.eye(n)) <= 1e-14 * n, (rep, b)
+            assert np.linalg.norm(Q[b] @ R[b] - S) <= 1e-14 * n * np.linalg.norm(S), (rep, b)
+            Rl = np.linalg.qr(S, mode="r")
+            s = np.sign(np.diag(R[b])) * np.sign(np.diag(Rl))
+            assert np.abs(R[b] * s[:, None] - Rl).max() <= 1e-12 * np.abs(Rl).max(), (rep, b)
+
+
 @pytest.mark.parametrize("m,n", [(100, 100), (333, 129), (64, 1)])
 def test_plain_qr(z, m, n):
     rng = np.random.default_rng(3 * m + n)

@@ -150,3 +150,38 @@ def test_svd(z):
     assert np.allclose(S, s, rtol=1e-10, atol=1e-14)   # eigenvalues: absolute error ~ eps ||H||
     assert oz.svd_residual_paper(A, Uc, S, Vc) <= 1e-13
     assert oz.orth_paper(Uc) <= 1e-14 and oz.orth_paper(Vc) <= 1e-14
+
+
+def test_batched_uneven(z):
+    # Many matrices of different shapes, kappa and degree in one call.
+    specs = W.batch_specs(count=12, seed=4100, nmin=20, nmax=140, kmin=2.0, kmax=12.0)
+    mats = [W.svd_matrix(sp["m"], sp["n"], sp["kappa"], sp["seed_u"], sp["seed_v"])[0] for sp in specs]
+    ls = [1.0 / sp["kappa"] for sp in specs]
+    rs = [None] * len(specs)
+    from oracle import coeffs as oc
+    rs = [oc.choose_r(l) for l in ls]
+    Qs, Hs, infos = z.pd_batched([dev(A) for A in mats], alphas=[1.0] * len(mats), ls=ls, rs=rs)
+    for A, Q, H, inf, l, r in zip(mats, Qs, Hs, infos, ls, rs):
+        Q, H = Q.cpu().numpy(), H.cpu().numpy()
+        Qo, Ho, io = oz.zolo_pd(A, 1.0, l, r)
+        assert inf["status"] == 0
+        same_schedule(inf, io)
+        assert oz.backward_error(A, Q, H) <= BAR and oz.orthogonality(Q) <= BAR
+        assert np.linalg.norm(H - Ho) / np.linalg.norm(Ho) <= 1e-12
+
+
+def test_batched_mid_sizes(z):
+    # Matrices of the 512-matrix uneven workload with n = 600..1000 (panels
+    # spread over 10-18 workgroups each), solved in one batched call.  Exact
+    # H = V diag(sigma) V^T is known from the construction.
+    specs = W.batch_specs(count=512, seed=4000)
+    pick = [specs[i] for i in (127, 143, 195, 268)]
+    built = [W.svd_matrix(sp["m"], sp["n"], sp["kappa"], sp["seed_u"], sp["seed_v"]) for sp in pick]
+    ls = [1.0 / sp["kappa"] for sp in pick]
+    Qs, Hs, infos = z.pd_batched([dev(b[0]) for b in built], alphas=[1.0] * len(pick), ls=ls)
+    for (A, U, sig, V), Q, H, inf in zip(built, Qs, Hs, infos):
+        Q, H = Q.cpu().numpy(), H.cpu().numpy()
+        assert inf["status"] == 0, inf
+        assert oz.backward_error(A, Q, H) <= BAR and oz.orthogonality(Q) <= BAR
+        Hx = (V * sig) @ V.T
+        assert np.linalg.norm(H - Hx) / np.linalg.norm(Hx) <= 1e-12
