@@ -102,6 +102,52 @@ def bench_batched(args):
     z.close()
 
 
+def bench_precision_study(args):
+    """FP64 vs mixed (FP32 middle Cholesky-type steps) on the n x n generator at
+    kappa in {1e4, 1e8, 1e12} with degree r (default 3, which leaves a middle
+    step); U and V are shared across kappa."""
+    import numpy as np
+    import torch
+    from paper_1806_06204_amd import workloads as W
+    from paper_1806_06204_amd import zolo
+    n, r = args.n, args.r
+    print(f"[bench] generating Haar factors n={n}", file=sys.stderr, flush=True)
+    U = W.haar(n, n, 1000 + 1)
+    V = W.haar(n, n, 2000 + 1)
+    z = zolo.Zolo()
+    rows = []
+    for kappa in (1e4, 1e8, 1e12):
+        sigma = W.logspaced_sigma(n, kappa)
+        A = torch.from_numpy(np.ascontiguousarray(((U * sigma) @ V.T).T)).to("cuda:0").t()
+        row = {"kappa": kappa}
+        for prec_name, prec in (("fp64", 0), ("mixed", 1)):
+            for _ in range(args.warmup):
+                z.pd(A, alpha=1.0, l=1.0 / kappa, r=r, precision=prec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                _, _, info = z.pd(A, alpha=1.0, l=1.0 / kappa, r=r, precision=prec)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / args.steps
+            _, _, e = z.pd(A, alpha=1.0, l=1.0 / kappa, r=r, precision=prec, compute_errors=1)
+            row[prec_name] = {"ms": dt * 1e3, "schedule": "".join(info["kinds"]), "prec": info["prec"],
+                              "bwd_err": e["bwd_err"], "orth_err": e["orth_err"],
+                              "meets_1e-13": bool(e["bwd_err"] <= 1e-13 and e["orth_err"] <= 1e-13)}
+            print(f"[bench] kappa={kappa:g} {prec_name}: {dt * 1e3:.1f} ms {row[prec_name]}", file=sys.stderr,
+                  flush=True)
+        row["mixed_speedup"] = row["fp64"]["ms"] / row["mixed"]["ms"]
+        rows.append(row)
+        del A
+    out = {"metric": "Zolo-PD mixed vs FP64 time and backward error", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "dtype": "f64+f32", "data": "synthetic",
+           "config": {"workload": f"{n}x{n} A = U diag(sigma) V^T, sigma log-spaced 1..1/kappa, r={r}, "
+                                  "alpha=1, l=1/kappa; mixed = FP32 for Cholesky-type steps not predicted last",
+                      "n": n, "r": r},
+           "rows": rows}
+    print(json.dumps(out), flush=True)
+    z.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +158,8 @@ def main():
     ap.add_argument("--r", type=int, default=8)
     ap.add_argument("--cpu-sample", type=int, default=640)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision-study", action="store_true",
+                    help="instead: FP64 vs mixed at kappa 1e4/1e8/1e12 (use with --r 3)")
     ap.add_argument("--batched", type=int, default=0,
                     help="instead: Zolo-PD of this many uneven matrices (n in [64,1024], m in [n,2n], "
                          "kappa log-uniform in [1e2,1e12]) in one zolo_pd_batched call")
@@ -128,6 +176,8 @@ def main():
 
     if args.batched:
         return bench_batched(args)
+    if args.precision_study:
+        return bench_precision_study(args)
     n, kappa, r = args.n, args.kappa, args.r
     print(f"[bench] generating {n}x{n} kappa={kappa:g} input", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
@@ -174,6 +224,12 @@ def main():
     h_err = float(np.max(np.abs(Hs[idx[:, 0], idx[:, 1]] - h_exact)) / np.max(sigma))
     del Qp, H
 
+    # The mixed schedule at this configuration (FP32 only for Cholesky-type
+    # steps that are not predicted to be the last one).
+    _, _, minfo = z.pd(A, alpha=1.0, l=l, r=r, precision=1)
+    mixed = {"schedule": "".join(minfo["kinds"]), "prec": minfo["prec"], "ms": minfo["t_stage_ms"][7],
+             "note": "no FP32 step at this configuration" if set(minfo["prec"]) == {"d"} else "has FP32 steps"}
+
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
@@ -214,6 +270,7 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
                      "launches_per_step": launches / args.steps,
                      "mean_launch_ms": ms / launches},
+        "mixed": mixed,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

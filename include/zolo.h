@@ -71,8 +71,17 @@ typedef struct {
     int qr_variant;      /* 0 (default, the only value accepted): structured QR of
                             [X; sqrt(c) I] with m + NB live rows per panel
                             (Section 3.1) */
-    int precision;       /* 0 (default): every step in FP64.  Other values are
-                            rejected (-argument) in this version. */
+    int precision;       /* 0 (default): every step in FP64.
+                            1 mixed: every Cholesky-type step that is not
+                            predicted to be the last (l_next < 1 - 1e-15) runs
+                            in FP32 on the FP32 matrix cores; QR-type steps, the
+                            last step, the stop checks and H stay in FP64.
+                            An FP32 step perturbs the iterate by about the FP32
+                            unit roundoff and later steps converge to the polar
+                            factor of the perturbed iterate, so Qp stays
+                            orthogonal to FP64 accuracy but the backward error
+                            is of FP32 size (about 1e-7) whenever a step ran in
+                            FP32.  info->prec says which steps did. */
     int compute_errors;  /* 1: fill info->bwd_err and info->orth_err (costs two
                             extra GEMMs); 0 (default): leave them at -1 */
     int reserved[9];
@@ -85,6 +94,7 @@ typedef struct {
     int r_used;            /* Zolotarev degree r */
     int chol_fallbacks;    /* Cholesky-type steps redone as QR-type */
     char kind[ZOLO_MAX_ITER + 1];  /* 'Q' or 'C' per iteration, NUL-terminated */
+    char prec[ZOLO_MAX_ITER + 1];  /* 'd' (FP64) or 's' (FP32) per iteration */
     double alpha;          /* scaling alpha >= sigma_max(A) used, X0 = A / alpha */
     double l0;             /* l used for the first step (after clamping) */
     double l_seq[ZOLO_MAX_ITER];   /* l before each step */

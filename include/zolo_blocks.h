@@ -1,9 +1,11 @@
 /*
  * zolo_blocks.h - building blocks of the Zolo-PD library, exported for
- * kernel-level checks and benchmarks.  Same conventions as zolo.h: FP64,
- * column-major, device pointers for matrices, host pointers for scalar arrays,
- * work queued on the handle's stream and complete on return, LAPACK-style
- * negative return for an invalid argument, 4 for a HIP error.
+ * kernel-level checks and benchmarks.  Same conventions as zolo.h: FP64
+ * (the zolo_s* variants: FP32, the precision of the FP32 steps of the mixed
+ * schedule, zolo_opts.precision = 1), column-major, device pointers for
+ * matrices, host pointers for scalar arrays, work queued on the handle's
+ * stream and complete on return, LAPACK-style negative return for an invalid
+ * argument, 4 for a HIP error.
  */
 #ifndef ZOLO_BLOCKS_H
 #define ZOLO_BLOCKS_H
@@ -24,6 +26,12 @@ int zolo_dgemm(zolo_handle h, int transa, int transb, int m, int n, int k, doubl
                const double* A, int lda, long long strideA, const double* B, int ldb, long long strideB,
                double beta, double* C, int ldc, long long strideC, int batch);
 
+/* The same product in FP32 on the FP32 matrix cores (the X^T X, factor and
+ * X F products of an FP32 Cholesky-type step of the mixed schedule). */
+int zolo_sgemm(zolo_handle h, int transa, int transb, int m, int n, int k, float alpha,
+               const float* A, int lda, long long strideA, const float* B, int ldb, long long strideB,
+               float beta, float* C, int ldc, long long strideC, int batch);
+
 /* Upper Cholesky Z_b = R_b^T R_b, in place, for b < batch (the factorisation
  * of Z_{2j-1} = X^T X + c_{2j-1} I in Algorithm 1 step 4(d), with R the factor
  * the paper calls L).  The strict lower triangle is set to zero.
@@ -31,10 +39,17 @@ int zolo_dgemm(zolo_handle h, int transa, int transb, int m, int n, int k, doubl
  * pivot; the return value is ZOLO_BREAKDOWN if any info[b] != 0. */
 int zolo_dpotrf_batched(zolo_handle h, int n, double* Z, int ldz, long long strideZ, int batch, int* info);
 
+/* FP32 variant of zolo_dpotrf_batched (same arguments and results). */
+int zolo_spotrf_batched(zolo_handle h, int n, float* Z, int ldz, long long strideZ, int batch, int* info);
+
 /* Rinv_b = R_b^{-1} for upper-triangular R_b (strict lower part of Rinv
  * zero), for b < batch.  Used to form X (X^T X + c I)^{-1} in eq. (11). */
 int zolo_dtrtri_batched(zolo_handle h, int n, const double* R, int ldr, long long strideR,
                         double* Rinv, int ldi, long long strideI, int batch);
+
+/* FP32 variant of zolo_dtrtri_batched. */
+int zolo_strtri_batched(zolo_handle h, int n, const float* R, int ldr, long long strideR,
+                        float* Rinv, int ldi, long long strideI, int batch);
 
 /* Structured Householder QR of the stacked [Y_b; p_b I] ((m + n) x n), or a
  * plain Householder QR of Y_b (m x n, m >= n) when pivots is NULL, for

@@ -39,12 +39,9 @@ int sync_status(zolo_handle h, hipError_t e) {
     return hipStreamSynchronize(h->stream) == hipSuccess ? 0 : ZOLO_HIP;
 }
 
-}  // namespace
-
-extern "C" {
-
-int zolo_dgemm(zolo_handle h, int transa, int transb, int m, int n, int k, double alpha, const double* A, int lda,
-               long long strideA, const double* B, int ldb, long long strideB, double beta, double* C, int ldc,
+template <class T>
+int gemm_entry(zolo_handle h, int transa, int transb, int m, int n, int k, double alpha, const T* A, int lda,
+               long long strideA, const T* B, int ldb, long long strideB, double beta, T* C, int ldc,
                long long strideC, int batch) {
     if (!h) return -1;
     if (m < 0) return -4;
@@ -57,7 +54,7 @@ int zolo_dgemm(zolo_handle h, int transa, int transb, int m, int n, int k, doubl
     if (!C && m * (long long)n > 0) return -15;
     if (ldc < std::max(1, m)) return -16;
     if (batch < 0) return -18;
-    GemmDesc g;
+    GemmDescT<T> g;
     g.m = m; g.n = n; g.k = k; g.transa = transa != 0; g.transb = transb != 0;
     g.A = A; g.lda = lda; g.strideA = strideA;
     g.B = B; g.ldb = ldb; g.strideB = strideB;
@@ -67,7 +64,8 @@ int zolo_dgemm(zolo_handle h, int transa, int transb, int m, int n, int k, doubl
     return sync_status(h, gemm(g, h->stream));
 }
 
-int zolo_dpotrf_batched(zolo_handle h, int n, double* Z, int ldz, long long strideZ, int batch, int* info) {
+template <class T>
+int potrf_entry(zolo_handle h, int n, T* Z, int ldz, long long strideZ, int batch, int* info) {
     if (!h) return -1;
     if (n < 1) return -2;
     if (!Z) return -3;
@@ -75,11 +73,11 @@ int zolo_dpotrf_batched(zolo_handle h, int n, double* Z, int ldz, long long stri
     if (batch < 1) return -6;
     if (!info) return -7;
     size_t off = 0;
-    const size_t need = 256 + 64 * 64 * 8 * (size_t)batch + 256 + sizeof(int) * batch + 512;
+    const size_t need = 256 + 64 * 64 * sizeof(T) * (size_t)batch + 256 + sizeof(int) * batch + 512;
     if (int rc = grow(h, need)) return rc;
-    double* work = (double*)bump(h->arena, off, 64 * 64 * 8 * (size_t)batch);
+    T* work = (T*)bump(h->arena, off, 64 * 64 * sizeof(T) * (size_t)batch);
     int* dinfo = (int*)bump(h->arena, off, sizeof(int) * batch);
-    hipError_t e = potrf_batched(n, Z, ldz, strideZ, batch, dinfo, work, h->stream);
+    hipError_t e = potrf_batched<T>(n, Z, ldz, strideZ, batch, dinfo, work, h->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(info, dinfo, sizeof(int) * batch, hipMemcpyDeviceToHost, h->stream);
     if (int rc = sync_status(h, e)) return rc;
     for (int b = 0; b < batch; ++b)
@@ -87,8 +85,9 @@ int zolo_dpotrf_batched(zolo_handle h, int n, double* Z, int ldz, long long stri
     return 0;
 }
 
-int zolo_dtrtri_batched(zolo_handle h, int n, const double* R, int ldr, long long strideR, double* Rinv, int ldi,
-                        long long strideI, int batch) {
+template <class T>
+int trtri_entry(zolo_handle h, int n, const T* R, int ldr, long long strideR, T* Rinv, int ldi, long long strideI,
+                int batch) {
     if (!h) return -1;
     if (n < 1) return -2;
     if (!R) return -3;
@@ -98,10 +97,46 @@ int zolo_dtrtri_batched(zolo_handle h, int n, const double* R, int ldr, long lon
     if (batch < 1) return -9;
     const long long work_elems = (long long)n * n * batch / 2 + 64 * 64 * (long long)batch + 64;
     size_t off = 0;
-    if (int rc = grow(h, 512 + sizeof(double) * (size_t)work_elems)) return rc;
-    double* work = (double*)bump(h->arena, off, sizeof(double) * (size_t)work_elems);
-    return sync_status(h, trtri_batched(n, R, ldr, strideR, Rinv, ldi, strideI, batch, work, work_elems,
-                                        h->stream));
+    if (int rc = grow(h, 512 + sizeof(T) * (size_t)work_elems)) return rc;
+    T* work = (T*)bump(h->arena, off, sizeof(T) * (size_t)work_elems);
+    return sync_status(h, trtri_batched<T>(n, R, ldr, strideR, Rinv, ldi, strideI, batch, work, work_elems,
+                                           h->stream));
+}
+
+}  // namespace
+
+extern "C" {
+
+int zolo_dgemm(zolo_handle h, int transa, int transb, int m, int n, int k, double alpha, const double* A, int lda,
+               long long strideA, const double* B, int ldb, long long strideB, double beta, double* C, int ldc,
+               long long strideC, int batch) {
+    return gemm_entry<double>(h, transa, transb, m, n, k, alpha, A, lda, strideA, B, ldb, strideB, beta, C, ldc,
+                              strideC, batch);
+}
+
+int zolo_sgemm(zolo_handle h, int transa, int transb, int m, int n, int k, float alpha, const float* A, int lda,
+               long long strideA, const float* B, int ldb, long long strideB, float beta, float* C, int ldc,
+               long long strideC, int batch) {
+    return gemm_entry<float>(h, transa, transb, m, n, k, alpha, A, lda, strideA, B, ldb, strideB, beta, C, ldc,
+                             strideC, batch);
+}
+
+int zolo_dpotrf_batched(zolo_handle h, int n, double* Z, int ldz, long long strideZ, int batch, int* info) {
+    return potrf_entry<double>(h, n, Z, ldz, strideZ, batch, info);
+}
+
+int zolo_spotrf_batched(zolo_handle h, int n, float* Z, int ldz, long long strideZ, int batch, int* info) {
+    return potrf_entry<float>(h, n, Z, ldz, strideZ, batch, info);
+}
+
+int zolo_dtrtri_batched(zolo_handle h, int n, const double* R, int ldr, long long strideR, double* Rinv, int ldi,
+                        long long strideI, int batch) {
+    return trtri_entry<double>(h, n, R, ldr, strideR, Rinv, ldi, strideI, batch);
+}
+
+int zolo_strtri_batched(zolo_handle h, int n, const float* R, int ldr, long long strideR, float* Rinv, int ldi,
+                        long long strideI, int batch) {
+    return trtri_entry<float>(h, n, R, ldr, strideR, Rinv, ldi, strideI, batch);
 }
 
 int zolo_structured_qr_batched(zolo_handle h, int m, int n, const double* pivots, double* M, int ldm,

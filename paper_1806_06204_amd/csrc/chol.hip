@@ -1,6 +1,7 @@
-// Batched upper Cholesky and triangular inverse for the Cholesky-type step of
-// Zolo-PD (Algorithm 1 step 4(d)): Z_j = X^T X + c_{2j-1} I = R_j^T R_j for all
-// j at once, then R_j^{-1}.
+// Batched upper Cholesky and triangular inverse (FP64, and FP32 for the mixed
+// precision schedule) for the Cholesky-type step of Zolo-PD (Algorithm 1
+// step 4(d)): Z_j = X^T X + c_{2j-1} I = R_j^T R_j for all j at once, then
+// R_j^{-1}.
 //
 // POTRF is right-looking with 64-column blocks: a 64 x 64 diagonal block is
 // factored in LDS by one workgroup per matrix (which also inverts it), the row
@@ -22,41 +23,43 @@ constexpr int kB = 64;
 
 // Inverse of the upper-triangular kb x kb matrix S (LDS) into Si (LDS):
 // thread j back-substitutes column j.
-__device__ void lds_upper_inverse(int kb, const double (*S)[kB + 1], double (*Si)[kB + 1]) {
+template <class T>
+__device__ void lds_upper_inverse(int kb, const T (*S)[kB + 1], T (*Si)[kB + 1]) {
     const int j = threadIdx.x;
     if (j < kB) {
-        for (int i = kB - 1; i > j; --i) Si[i][j] = 0.0;
+        for (int i = kB - 1; i > j; --i) Si[i][j] = 0;
         if (j < kb) {
             for (int i = j; i >= 0; --i) {
-                double s = (i == j) ? 1.0 : 0.0;
+                T s = (i == j) ? 1 : 0;
                 for (int k = i + 1; k <= j; ++k) s -= S[i][k] * Si[k][j];
                 Si[i][j] = s / S[i][i];
             }
         } else {
-            for (int i = 0; i <= j; ++i) Si[i][j] = (i == j) ? 1.0 : 0.0;
+            for (int i = 0; i <= j; ++i) Si[i][j] = (i == j) ? 1 : 0;
         }
     }
 }
 
-__global__ __launch_bounds__(256) void potrf_diag_kernel(int k0, int kb, double* Z, long long ldz, long long sz,
-                                                         int* info, double* work) {
-    __shared__ double S[kB][kB + 1];
-    __shared__ double Si[kB][kB + 1];
+template <class T>
+__global__ __launch_bounds__(256) void potrf_diag_kernel(int k0, int kb, T* Z, long long ldz, long long sz,
+                                                         int* info, T* work) {
+    __shared__ T S[kB][kB + 1];
+    __shared__ T Si[kB][kB + 1];
     __shared__ int s_bad;
     const int b = blockIdx.x, tid = threadIdx.x;
-    double* Zb = Z + b * sz + k0 + (long long)k0 * ldz;
+    T* Zb = Z + b * sz + k0 + (long long)k0 * ldz;
     for (int e = tid; e < kB * kB; e += 256) {
         const int i = e % kB, j = e / kB;
-        S[i][j] = (i < kb && j < kb && i <= j) ? Zb[i + (long long)j * ldz] : 0.0;
+        S[i][j] = (i < kb && j < kb && i <= j) ? Zb[i + (long long)j * ldz] : (T)0;
     }
     if (tid == 0) s_bad = 0;
     __syncthreads();
     for (int k = 0; k < kb; ++k) {
         if (tid == 0) {
-            double d = S[k][k];
-            if (!(d > 0.0) || !isfinite(d)) {
+            T d = S[k][k];
+            if (!(d > (T)0) || !isfinite(d)) {
                 if (s_bad == 0) s_bad = k0 + k + 1;
-                d = 1.0;  // keep going so every wave finishes; the caller discards the result
+                d = 1;  // keep going so every wave finishes; the caller discards the result
             }
             S[k][k] = sqrt(d);
         }
@@ -72,11 +75,11 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(int k0, int kb, double*
     }
     for (int e = tid; e < kb * kb; e += 256) {
         const int i = e % kb, j = e / kb;
-        Zb[i + (long long)j * ldz] = (i <= j) ? S[i][j] : 0.0;
+        Zb[i + (long long)j * ldz] = (i <= j) ? S[i][j] : (T)0;
     }
-    lds_upper_inverse(kb, S, Si);
+    lds_upper_inverse<T>(kb, S, Si);
     __syncthreads();
-    double* wb = work + (long long)b * kB * kB;
+    T* wb = work + (long long)b * kB * kB;
     for (int e = tid; e < kB * kB; e += 256) {
         const int i = e % kB, j = e / kB;
         wb[e] = Si[i][j];
@@ -85,20 +88,21 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(int k0, int kb, double*
 }
 
 // Invert every 64 x 64 diagonal block of R_b into Rinv_b.
-__global__ __launch_bounds__(256) void trtri_diag_kernel(int n, const double* R, long long ldr, long long sr,
-                                                         double* Rinv, long long ldi, long long si) {
-    __shared__ double S[kB][kB + 1];
-    __shared__ double Si[kB][kB + 1];
+template <class T>
+__global__ __launch_bounds__(256) void trtri_diag_kernel(int n, const T* R, long long ldr, long long sr, T* Rinv,
+                                                         long long ldi, long long si) {
+    __shared__ T S[kB][kB + 1];
+    __shared__ T Si[kB][kB + 1];
     const int blk = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
     const int o = blk * kB, kb = min(kB, n - o);
-    const double* Rb = R + b * sr + o + (long long)o * ldr;
-    double* Ib = Rinv + b * si + o + (long long)o * ldi;
+    const T* Rb = R + b * sr + o + (long long)o * ldr;
+    T* Ib = Rinv + b * si + o + (long long)o * ldi;
     for (int e = tid; e < kB * kB; e += 256) {
         const int i = e % kB, j = e / kB;
-        S[i][j] = (i < kb && j < kb && i <= j) ? Rb[i + (long long)j * ldr] : (i == j ? 1.0 : 0.0);
+        S[i][j] = (i < kb && j < kb && i <= j) ? Rb[i + (long long)j * ldr] : (T)(i == j ? 1 : 0);
     }
     __syncthreads();
-    lds_upper_inverse(kb, S, Si);
+    lds_upper_inverse<T>(kb, S, Si);
     __syncthreads();
     for (int e = tid; e < kb * kb; e += 256) {
         const int i = e % kb, j = e / kb;
@@ -108,21 +112,23 @@ __global__ __launch_bounds__(256) void trtri_diag_kernel(int n, const double* R,
 
 }  // namespace
 
-hipError_t potrf_batched(int n, double* Z, long long ldz, long long sz, int batch, int* info_dev, double* work,
+template <class T>
+hipError_t potrf_batched(int n, T* Z, long long ldz, long long sz, int batch, int* info_dev, T* work,
                          hipStream_t st) {
     hipError_t e = hipMemsetAsync(info_dev, 0, sizeof(int) * batch, st);
     if (e != hipSuccess) return e;
     for (int k0 = 0; k0 < n; k0 += kB) {
         const int kb = n - k0 < kB ? n - k0 : kB;
-        StatScope sc("potrf_diag_kernel", st, batch * (double)kb * kb * kb / 3.0);
-        potrf_diag_kernel<<<batch, 256, 0, st>>>(k0, kb, Z, ldz, sz, info_dev, work);
+        StatScope sc(sizeof(T) == 8 ? "potrf_diag_kernel<double>" : "potrf_diag_kernel<float>", st,
+                     batch * (double)kb * kb * kb / 3.0);
+        potrf_diag_kernel<T><<<batch, 256, 0, st>>>(k0, kb, Z, ldz, sz, info_dev, work);
         sc.end();
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const int rest = n - k0 - kb;
         if (rest <= 0) break;
-        double* Z12 = Z + k0 + (long long)(k0 + kb) * ldz;
+        T* Z12 = Z + k0 + (long long)(k0 + kb) * ldz;
         // R12 = R_kk^{-T} Z12, in place (one tile row covers all kb rows).
-        GemmDesc g;
+        GemmDescT<T> g;
         g.m = kb; g.n = rest; g.k = kb; g.transa = 1; g.transb = 0;
         g.A = work; g.lda = kB; g.strideA = (long long)kB * kB;
         g.B = Z12; g.ldb = ldz; g.strideB = sz;
@@ -130,8 +136,8 @@ hipError_t potrf_batched(int n, double* Z, long long ldz, long long sz, int batc
         g.beta = 0.0; g.batch = batch; g.flags = kALower;
         if ((e = gemm(g, st)) != hipSuccess) return e;
         // Z22 -= R12^T R12 on the upper tiles.
-        double* Z22 = Z + (k0 + kb) + (long long)(k0 + kb) * ldz;
-        GemmDesc s;
+        T* Z22 = Z + (k0 + kb) + (long long)(k0 + kb) * ldz;
+        GemmDescT<T> s;
         s.m = rest; s.n = rest; s.k = kb; s.transa = 1; s.transb = 0;
         s.A = Z12; s.lda = ldz; s.strideA = sz;
         s.B = Z12; s.ldb = ldz; s.strideB = sz;
@@ -141,15 +147,18 @@ hipError_t potrf_batched(int n, double* Z, long long ldz, long long sz, int batc
         s.flags = kCUpperTiles | kCStoreUpper;
         if ((e = gemm(s, st)) != hipSuccess) return e;
     }
-    return zero_strict_lower(n, Z, ldz, sz, batch, st);
+    return zero_strict_lower<T>(n, Z, ldz, sz, batch, st);
 }
+template hipError_t potrf_batched<double>(int, double*, long long, long long, int, int*, double*, hipStream_t);
+template hipError_t potrf_batched<float>(int, float*, long long, long long, int, int*, float*, hipStream_t);
 
-hipError_t trtri_batched(int n, const double* R, long long ldr, long long sr, double* Rinv, long long ldi,
-                         long long si, int batch, double* work, long long work_elems, hipStream_t st) {
-    hipError_t e = fill_matrix(n, n, Rinv, ldi, si, batch, 0.0, 0.0, st);
+template <class T>
+hipError_t trtri_batched(int n, const T* R, long long ldr, long long sr, T* Rinv, long long ldi, long long si,
+                         int batch, T* work, long long work_elems, hipStream_t st) {
+    hipError_t e = fill_matrix<T>(n, n, Rinv, ldi, si, batch, 0.0, 0.0, st);
     if (e != hipSuccess) return e;
     const int nblk = (n + kB - 1) / kB;
-    trtri_diag_kernel<<<dim3(nblk, batch), 256, 0, st>>>(n, R, ldr, sr, Rinv, ldi, si);
+    trtri_diag_kernel<T><<<dim3(nblk, batch), 256, 0, st>>>(n, R, ldr, sr, Rinv, ldi, si);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     for (long long s = kB; s < n; s *= 2) {
         const long long full = n / (2 * s);           // pairs with both blocks of size s
@@ -162,9 +171,9 @@ hipError_t trtri_batched(int n, const double* R, long long ldr, long long sr, do
             if (npairs == 0) continue;
             const long long o = part == 0 ? 0 : o_rag;
             const long long s2 = part == 0 ? s : s2_rag;
-            double* Wp = work + (part == 0 ? 0 : full * s * s);
+            T* Wp = work + (part == 0 ? 0 : full * s * s);
             // W = R12 * R22^{-1}
-            GemmDesc g;
+            GemmDescT<T> g;
             g.m = (int)s; g.n = (int)s2; g.k = (int)s2;
             g.A = R + o + (o + s) * ldr; g.lda = ldr; g.strideA = 2 * s * (ldr + 1);
             g.B = Rinv + (o + s) + (o + s) * ldi; g.ldb = ldi; g.strideB = 2 * s * (ldi + 1);
@@ -173,7 +182,7 @@ hipError_t trtri_batched(int n, const double* R, long long ldr, long long sr, do
             g.batch2 = batch; g.strideA2 = sr; g.strideB2 = si; g.strideC2 = per_b;
             if ((e = gemm(g, st)) != hipSuccess) return e;
             // Rinv12 = -R11^{-1} W
-            GemmDesc h;
+            GemmDescT<T> h;
             h.m = (int)s; h.n = (int)s2; h.k = (int)s;
             h.A = Rinv + o + o * ldi; h.lda = ldi; h.strideA = 2 * s * (ldi + 1);
             h.B = Wp; h.ldb = s; h.strideB = s * s2;
@@ -185,5 +194,10 @@ hipError_t trtri_batched(int n, const double* R, long long ldr, long long sr, do
     }
     return hipSuccess;
 }
+
+template hipError_t trtri_batched<double>(int, const double*, long long, long long, double*, long long, long long,
+                                          int, double*, long long, hipStream_t);
+template hipError_t trtri_batched<float>(int, const float*, long long, long long, float*, long long, long long, int,
+                                         float*, long long, hipStream_t);
 
 }  // namespace zolo

@@ -11,6 +11,7 @@
 namespace zolo {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kWave = 64;
 
@@ -34,13 +35,15 @@ enum GemmFlags : unsigned {
 
 constexpr int kMaxInlineAlpha = 16;
 
-struct GemmDesc {
+// T = double (FP64 path) or float (the FP32 steps of the mixed schedule).
+template <class T>
+struct GemmDescT {
     int m = 0, n = 0, k = 0;
     int transa = 0, transb = 0;
-    const double* A = nullptr; long long lda = 0, strideA = 0;
-    const double* B = nullptr; long long ldb = 0, strideB = 0;
-    const double* Cin = nullptr; long long ldcin = 0, strideCin = 0;
-    double* C = nullptr; long long ldc = 0, strideC = 0;
+    const T* A = nullptr; long long lda = 0, strideA = 0;
+    const T* B = nullptr; long long ldb = 0, strideB = 0;
+    const T* Cin = nullptr; long long ldcin = 0, strideCin = 0;
+    T* C = nullptr; long long ldc = 0, strideC = 0;
     double alpha = 1.0;
     double beta = 0.0;
     int batch = 1;
@@ -52,13 +55,26 @@ struct GemmDesc {
     int nalpha = 0;          // if > 0, alpha_b = alphas[b] (b < nalpha <= 16)
     double alphas[kMaxInlineAlpha] = {};
 };
+using GemmDesc = GemmDescT<double>;
+using SGemmDesc = GemmDescT<float>;
 
 // Launches D = ... on `stream`.  Returns hipSuccess or the launch error.
 hipError_t gemm(const GemmDesc& d, hipStream_t stream);
+hipError_t gemm(const SGemmDesc& d, hipStream_t stream);
 
 // Rough count of the floating-point operations a descriptor executes
 // (2 m n k per product, halved per triangular operand / upper-tile output).
-double gemm_flops(const GemmDesc& d);
+template <class T>
+double gemm_flops(const GemmDescT<T>& d) {
+    double f = 2.0 * d.m * (double)d.n * d.k * d.batch * d.batch2;
+    int tri = 0;
+    if (d.flags & (kAUpper | kALower)) ++tri;
+    if (d.flags & (kBUpper | kBLower)) ++tri;
+    if (tri == 1) f *= 0.5;
+    if (tri == 2) f /= 3.0;
+    if (d.flags & kCUpperTiles) f *= 0.5;
+    return f;
+}
 
 // ---------------------------------------------------------------------------
 // Small device helpers
@@ -66,6 +82,21 @@ double gemm_flops(const GemmDesc& d);
 __device__ inline d4 mfma_f64_16x16x4(double a, double b, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+
+// 16 x 16 x 4 MFMA tiles for either precision.  Both take A[l % 16][l / 16]
+// and B[l / 16][l % 16] from lane l; the accumulator rows differ:
+// FP64 holds D[l / 16 + 4 e][l % 16], FP32 holds D[4 (l / 16) + e][l % 16].
+template <class T> struct Mfma;
+template <> struct Mfma<double> {
+    typedef d4 acc;
+    __device__ static acc run(double a, double b, acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    __device__ static int row(int lane, int e) { return (lane >> 4) + 4 * e; }
+};
+template <> struct Mfma<float> {
+    typedef f4 acc;
+    __device__ static acc run(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static int row(int lane, int e) { return 4 * (lane >> 4) + e; }
+};
 
 __device__ inline double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

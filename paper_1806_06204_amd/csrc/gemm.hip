@@ -1,4 +1,5 @@
-// FP64 GEMM on CDNA4 matrix cores (v_mfma_f64_16x16x4f64).
+// GEMM on CDNA4 matrix cores: FP64 (v_mfma_f64_16x16x4f64) and, for the FP32
+// steps of the mixed precision schedule, FP32 (v_mfma_f32_16x16x4f32).
 //
 // Every BLAS3 phase of Zolo-PD (trailing updates and Q formation of the
 // structured QR, the Gram matrix X^T X, the Cholesky trailing updates,
@@ -10,8 +11,9 @@
 // in accumulator registers.  K is walked in BK = 16 slices staged through LDS
 // (k-major, so that a fragment load is 16 consecutive doubles); the next slice
 // is fetched into registers while the current one feeds the MFMAs.
-// Lane layout of v_mfma_f64_16x16x4f64 (lane l, accumulator element e):
-// A[l % 16][l / 16], B[l / 16][l % 16], D[l / 16 + 4 e][l % 16].  Tiles are
+// Lane layout (lane l, accumulator element e): A[l % 16][l / 16],
+// B[l / 16][l % 16]; D[l / 16 + 4 e][l % 16] for FP64, D[4 (l / 16) + e][l % 16]
+// for FP32.  Tiles are
 // ordered in groups of 8 tile-rows and the workgroup ids are remapped so that
 // neighbouring tiles run on the same XCD and reuse its L2.
 #include "common.hpp"
@@ -27,13 +29,14 @@ constexpr int kPad = 4;
 
 // 128 x 128 tiles hold 128 accumulator doubles per lane: one wave per SIMD
 // (512 registers); smaller tiles run two.
-template <int BM, int BN, bool TA, bool TB>
-__global__ __launch_bounds__(256, (BM * BN >= 128 * 128) ? 1 : 2) void dgemm_kernel(GemmDesc d) {
+template <class T, int BM, int BN, bool TA, bool TB>
+__global__ __launch_bounds__(256, (BM * BN >= 128 * 128) ? 1 : 2) void gemm_kernel(GemmDescT<T> d) {
+    typedef typename Mfma<T>::acc acc_t;
     constexpr int BK = kBK;
     constexpr int FM = BM / 32, FN = BN / 32;
     constexpr int APT = BM * BK / 256, BPT = BN * BK / 256;
-    __shared__ double As[2][BK][BM + kPad];
-    __shared__ double Bs[2][BK][BN + kPad];
+    __shared__ T As[2][BK][BM + kPad];
+    __shared__ T Bs[2][BK][BN + kPad];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave & 1) * (BM / 2), wn = (wave >> 1) * (BN / 2);
@@ -60,27 +63,27 @@ __global__ __launch_bounds__(256, (BM * BN >= 128 * 128) ? 1 : 2) void dgemm_ker
     const int bfirst = d.reduce ? 0 : blockIdx.y;
     const int ntiles = nk * nbatch;   // (batch, k) slices walked as one sequence
 
-    d4 acc[FM][FN];
+    acc_t acc[FM][FN];
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < FN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
     // Staging registers: raw loaded values, their validity bits and the
     // batch multiplier; masking and scaling happen at the LDS store so that
     // nothing consumes a load before the MFMAs of the current slice.
-    double ra[APT], rb[BPT];
+    T ra[APT], rb[BPT];
     unsigned amask = 0, bmask = 0;
-    double al_cur = 1.0;
+    T al_cur = 1;
     // Loads are unconditional from a clamped (always valid) address and then
     // masked with a select, so no branch separates them from the MFMAs.
     auto gload = [&](int t) {
         const int bi = t / nk;
         const int k0 = kb + (t - bi * nk) * BK;
         const int b = bfirst + bi;
-        const double* __restrict__ A = d.A + (long long)b * d.strideA + (long long)blockIdx.z * d.strideA2;
-        const double* __restrict__ B = d.B + (long long)b * d.strideB + (long long)blockIdx.z * d.strideB2;
-        al_cur = d.nalpha > 0 ? d.alphas[b] : 1.0;
+        const T* __restrict__ A = d.A + (long long)b * d.strideA + (long long)blockIdx.z * d.strideA2;
+        const T* __restrict__ B = d.B + (long long)b * d.strideB + (long long)blockIdx.z * d.strideB2;
+        al_cur = d.nalpha > 0 ? (T)d.alphas[b] : (T)1;
         amask = 0;
         bmask = 0;
 #pragma unroll
@@ -116,14 +119,14 @@ __global__ __launch_bounds__(256, (BM * BN >= 128 * 128) ? 1 : 2) void dgemm_ker
             const int e = tid + 256 * s;
             const int i = TA ? e / BK : e % BM;
             const int kk = TA ? e % BK : e / BM;
-            As[buf][kk][i] = (amask >> s) & 1u ? ra[s] * al_cur : 0.0;
+            As[buf][kk][i] = (amask >> s) & 1u ? ra[s] * al_cur : (T)0;
         }
 #pragma unroll
         for (int s = 0; s < BPT; ++s) {
             const int e = tid + 256 * s;
             const int j = TB ? e % BN : e / BK;
             const int kk = TB ? e / BN : e % BK;
-            Bs[buf][kk][j] = (bmask >> s) & 1u ? rb[s] : 0.0;
+            Bs[buf][kk][j] = (bmask >> s) & 1u ? rb[s] : (T)0;
         }
     };
 
@@ -136,7 +139,7 @@ __global__ __launch_bounds__(256, (BM * BN >= 128 * 128) ? 1 : 2) void dgemm_ker
             const int cur = t & 1;
 #pragma unroll
             for (int k4 = 0; k4 < BK; k4 += 4) {
-                double af[FM], bf[FN];
+                T af[FM], bf[FN];
                 const int kr = k4 + (lane >> 4);
 #pragma unroll
                 for (int i = 0; i < FM; ++i) af[i] = As[cur][kr][wm + i * 16 + (lane & 15)];
@@ -145,7 +148,7 @@ __global__ __launch_bounds__(256, (BM * BN >= 128 * 128) ? 1 : 2) void dgemm_ker
 #pragma unroll
                 for (int i = 0; i < FM; ++i)
 #pragma unroll
-                    for (int j = 0; j < FN; ++j) acc[i][j] = mfma_f64_16x16x4(af[i], bf[j], acc[i][j]);
+                    for (int j = 0; j < FN; ++j) acc[i][j] = Mfma<T>::run(af[i], bf[j], acc[i][j]);
             }
             if (t + 1 < ntiles) {
                 // The other buffer was last read in iteration t-1, before the
@@ -160,8 +163,9 @@ __global__ __launch_bounds__(256, (BM * BN >= 128 * 128) ? 1 : 2) void dgemm_ker
     }
 
     const int ob = d.reduce ? 0 : blockIdx.y;
-    double* __restrict__ C = d.C + (long long)ob * d.strideC + (long long)blockIdx.z * d.strideC2;
-    const double* Cin = d.Cin ? d.Cin + (long long)ob * d.strideCin + (long long)blockIdx.z * d.strideCin2 : nullptr;
+    T* __restrict__ C = d.C + (long long)ob * d.strideC + (long long)blockIdx.z * d.strideC2;
+    const T* Cin = d.Cin ? d.Cin + (long long)ob * d.strideCin + (long long)blockIdx.z * d.strideCin2 : nullptr;
+    const T alpha = (T)d.alpha, beta = (T)d.beta;
     const bool use_cin = Cin != nullptr && d.beta != 0.0;
 #pragma unroll
     for (int i = 0; i < FM; ++i)
@@ -169,42 +173,42 @@ __global__ __launch_bounds__(256, (BM * BN >= 128 * 128) ? 1 : 2) void dgemm_ker
         for (int j = 0; j < FN; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int gi = row0 + wm + i * 16 + (lane >> 4) + 4 * e;
+                const int gi = row0 + wm + i * 16 + Mfma<T>::row(lane, e);
                 const int gj = col0 + wn + j * 16 + (lane & 15);
                 bool ok = gi < d.m && gj < d.n;
                 if (fl & kCStoreUpper) ok = ok && gi <= gj;
                 if (fl & kCStoreLower) ok = ok && gi >= gj;
                 if (ok) {
-                    double v = d.alpha * acc[i][j][e];
-                    if (use_cin) v += d.beta * Cin[gi + (long long)gj * d.ldcin];
+                    T v = alpha * acc[i][j][e];
+                    if (use_cin) v += beta * Cin[gi + (long long)gj * d.ldcin];
                     C[gi + (long long)gj * d.ldc] = v;
                 }
             }
 }
 
-template <int BM, int BN>
-hipError_t launch_bm_bn(const GemmDesc& d, hipStream_t s) {
+template <class T, int BM, int BN>
+hipError_t launch_bm_bn(const GemmDescT<T>& d, hipStream_t s) {
     const int tiles = ((d.m + BM - 1) / BM) * ((d.n + BN - 1) / BN);
     dim3 grid(tiles, d.reduce ? 1 : d.batch, d.batch2);
     const int which = (d.transa ? 2 : 0) + (d.transb ? 1 : 0);
     char name[64];
     if (stats_on()) {
-        snprintf(name, sizeof(name), "dgemm_kernel<%d,%d,%c,%c>", BM, BN, d.transa ? 'T' : 'N', d.transb ? 'T' : 'N');
+        snprintf(name, sizeof(name), "%cgemm_kernel<%d,%d,%c,%c>", sizeof(T) == 8 ? 'd' : 's', BM, BN,
+                 d.transa ? 'T' : 'N', d.transb ? 'T' : 'N');
     } else {
         name[0] = 0;
     }
     StatScope sc(name, s, gemm_flops(d));
-    if (which == 0) dgemm_kernel<BM, BN, false, false><<<grid, 256, 0, s>>>(d);
-    else if (which == 1) dgemm_kernel<BM, BN, false, true><<<grid, 256, 0, s>>>(d);
-    else if (which == 2) dgemm_kernel<BM, BN, true, false><<<grid, 256, 0, s>>>(d);
-    else dgemm_kernel<BM, BN, true, true><<<grid, 256, 0, s>>>(d);
+    if (which == 0) gemm_kernel<T, BM, BN, false, false><<<grid, 256, 0, s>>>(d);
+    else if (which == 1) gemm_kernel<T, BM, BN, false, true><<<grid, 256, 0, s>>>(d);
+    else if (which == 2) gemm_kernel<T, BM, BN, true, false><<<grid, 256, 0, s>>>(d);
+    else gemm_kernel<T, BM, BN, true, true><<<grid, 256, 0, s>>>(d);
     sc.end();
     return hipGetLastError();
 }
 
-}  // namespace
-
-hipError_t gemm(const GemmDesc& d, hipStream_t s) {
+template <class T>
+hipError_t gemm_dispatch(const GemmDescT<T>& d, hipStream_t s) {
     if (d.m <= 0 || d.n <= 0) return hipSuccess;
     if (d.batch <= 0 || d.batch2 <= 0) return hipSuccess;
     if (d.nalpha > kMaxInlineAlpha || (d.nalpha > 0 && d.nalpha < d.batch)) return hipErrorInvalidValue;
@@ -213,21 +217,15 @@ hipError_t gemm(const GemmDesc& d, hipStream_t s) {
         (long long)((d.m + 127) / 128) * ((d.n + 127) / 128) * (d.reduce ? 1 : d.batch) * d.batch2;
     const bool small_m = d.m <= 64 || big_tiles < 256;
     const bool small_n = d.n <= 64 || big_tiles < 256;
-    if (small_m && small_n) return launch_bm_bn<64, 64>(d, s);
-    if (small_m) return launch_bm_bn<64, 128>(d, s);
-    if (small_n) return launch_bm_bn<128, 64>(d, s);
-    return launch_bm_bn<128, 128>(d, s);
+    if (small_m && small_n) return launch_bm_bn<T, 64, 64>(d, s);
+    if (small_m) return launch_bm_bn<T, 64, 128>(d, s);
+    if (small_n) return launch_bm_bn<T, 128, 64>(d, s);
+    return launch_bm_bn<T, 128, 128>(d, s);
 }
 
-double gemm_flops(const GemmDesc& d) {
-    double f = 2.0 * d.m * (double)d.n * d.k * d.batch * d.batch2;
-    int tri = 0;
-    if (d.flags & (kAUpper | kALower)) ++tri;
-    if (d.flags & (kBUpper | kBLower)) ++tri;
-    if (tri == 1) f *= 0.5;
-    if (tri == 2) f /= 3.0;
-    if (d.flags & kCUpperTiles) f *= 0.5;
-    return f;
-}
+}  // namespace
+
+hipError_t gemm(const GemmDesc& d, hipStream_t s) { return gemm_dispatch(d, s); }
+hipError_t gemm(const SGemmDesc& d, hipStream_t s) { return gemm_dispatch(d, s); }
 
 }  // namespace zolo

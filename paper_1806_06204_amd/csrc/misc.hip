@@ -52,46 +52,61 @@ __global__ void broadcast_copy_kernel(int m, int n, const double* __restrict__ X
 }
 
 // Z_b = G (upper triangle and diagonal) + shift_b I, strict lower part zero.
-__global__ void shift_copy_kernel(int n, const double* __restrict__ G, long long ldg,
-                                  double* __restrict__ Z, long long ldz, long long sz,
+template <class T>
+__global__ void shift_copy_kernel(int n, const T* __restrict__ G, long long ldg,
+                                  T* __restrict__ Z, long long ldz, long long sz,
                                   ShiftArgs sh) {
     const long long total = (long long)n * n;
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
          e += (long long)gridDim.x * blockDim.x) {
         const long long j = e / n, i = e - j * n;
-        const double g = i <= j ? G[i + j * ldg] : 0.0;
+        const T g = i <= j ? G[i + j * ldg] : (T)0;
         for (int b = 0; b < sh.batch; ++b)
-            Z[b * sz + i + j * ldz] = (i == j) ? g + sh.shift[b] : g;
+            Z[b * sz + i + j * ldz] = (i == j) ? g + (T)sh.shift[b] : g;
+    }
+}
+
+// Y = s * X with a change of precision (FP64 <-> FP32).
+template <class S, class D>
+__global__ void convert_kernel(int m, int n, const S* __restrict__ X, long long ldx, D* __restrict__ Y,
+                               long long ldy, double s) {
+    const long long total = (long long)m * n;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long j = e / m, i = e - j * m;
+        Y[i + j * ldy] = (D)(s * (double)X[i + j * ldx]);
     }
 }
 
 // Fill an n x n matrix (batched) with value `diag` on the diagonal and `off` elsewhere,
 // or only the strict lower triangle with zero (mode 1).
-__global__ void fill_kernel(int m, int n, double* __restrict__ Z, long long ldz, long long sz, int batch,
+template <class T>
+__global__ void fill_kernel(int m, int n, T* __restrict__ Z, long long ldz, long long sz, int batch,
                             int mode, double diag, double off) {
     const long long total = (long long)m * n;
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
          e += (long long)gridDim.x * blockDim.x) {
         const long long j = e / m, i = e - j * m;
         for (int b = 0; b < batch; ++b) {
-            double* p = Z + b * sz + i + j * ldz;
-            if (mode == 0) *p = (i == j) ? diag : off;
-            else if (i > j) *p = 0.0;
+            T* p = Z + b * sz + i + j * ldz;
+            if (mode == 0) *p = (T)((i == j) ? diag : off);
+            else if (i > j) *p = (T)0;
         }
     }
 }
 
 // S = (U + U^T)/2 from the upper triangle? mode 0: S = (C + C^T)/2 (full C);
 // mode 1: S[i][j] = C[min][max] + add_diag * delta_ij (mirror the upper triangle).
-__global__ void symmetrize_kernel(int n, const double* __restrict__ C, long long ldc,
-                                  double* __restrict__ S, long long lds, int mode, double add_diag) {
+template <class T>
+__global__ void symmetrize_kernel(int n, const T* __restrict__ C, long long ldc,
+                                  T* __restrict__ S, long long lds, int mode, double add_diag) {
     const long long total = (long long)n * n;
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
          e += (long long)gridDim.x * blockDim.x) {
         const long long j = e / n, i = e - j * n;
-        double v;
-        if (mode == 0) v = 0.5 * (C[i + j * ldc] + C[j + i * ldc]);
-        else v = (i <= j ? C[i + j * ldc] : C[j + i * ldc]) + (i == j ? add_diag : 0.0);
+        T v;
+        if (mode == 0) v = (T)0.5 * (C[i + j * ldc] + C[j + i * ldc]);
+        else v = (i <= j ? C[i + j * ldc] : C[j + i * ldc]) + (i == j ? (T)add_diag : (T)0);
         S[i + j * lds] = v;
     }
 }
@@ -249,28 +264,52 @@ hipError_t broadcast_copy(int m, int n, const double* X, long long ldx, double* 
     return hipGetLastError();
 }
 
-hipError_t shift_copy(int n, const double* G, long long ldg, double* Z, long long ldz, long long sz,
-                      const ShiftArgs& sh, hipStream_t st) {
-    shift_copy_kernel<<<grid_for((long long)n * n), kThreads, 0, st>>>(n, G, ldg, Z, ldz, sz, sh);
-    return hipGetLastError();
-}
-
-hipError_t fill_matrix(int m, int n, double* Z, long long ldz, long long sz, int batch, double diag, double off,
-                       hipStream_t st) {
-    fill_kernel<<<grid_for((long long)m * n), kThreads, 0, st>>>(m, n, Z, ldz, sz, batch, 0, diag, off);
-    return hipGetLastError();
-}
-
-hipError_t zero_strict_lower(int n, double* Z, long long ldz, long long sz, int batch, hipStream_t st) {
-    fill_kernel<<<grid_for((long long)n * n), kThreads, 0, st>>>(n, n, Z, ldz, sz, batch, 1, 0.0, 0.0);
-    return hipGetLastError();
-}
-
-hipError_t symmetrize(int n, const double* C, long long ldc, double* S, long long lds, int mode, double add_diag,
+template <class T>
+hipError_t shift_copy(int n, const T* G, long long ldg, T* Z, long long ldz, long long sz, const ShiftArgs& sh,
                       hipStream_t st) {
-    symmetrize_kernel<<<grid_for((long long)n * n), kThreads, 0, st>>>(n, C, ldc, S, lds, mode, add_diag);
+    shift_copy_kernel<T><<<grid_for((long long)n * n), kThreads, 0, st>>>(n, G, ldg, Z, ldz, sz, sh);
     return hipGetLastError();
 }
+template hipError_t shift_copy<double>(int, const double*, long long, double*, long long, long long,
+                                       const ShiftArgs&, hipStream_t);
+template hipError_t shift_copy<float>(int, const float*, long long, float*, long long, long long, const ShiftArgs&,
+                                      hipStream_t);
+
+template <class T>
+hipError_t fill_matrix(int m, int n, T* Z, long long ldz, long long sz, int batch, double diag, double off,
+                       hipStream_t st) {
+    fill_kernel<T><<<grid_for((long long)m * n), kThreads, 0, st>>>(m, n, Z, ldz, sz, batch, 0, diag, off);
+    return hipGetLastError();
+}
+template hipError_t fill_matrix<double>(int, int, double*, long long, long long, int, double, double, hipStream_t);
+template hipError_t fill_matrix<float>(int, int, float*, long long, long long, int, double, double, hipStream_t);
+
+template <class T>
+hipError_t zero_strict_lower(int n, T* Z, long long ldz, long long sz, int batch, hipStream_t st) {
+    fill_kernel<T><<<grid_for((long long)n * n), kThreads, 0, st>>>(n, n, Z, ldz, sz, batch, 1, 0.0, 0.0);
+    return hipGetLastError();
+}
+template hipError_t zero_strict_lower<double>(int, double*, long long, long long, int, hipStream_t);
+template hipError_t zero_strict_lower<float>(int, float*, long long, long long, int, hipStream_t);
+
+template <class T>
+hipError_t symmetrize(int n, const T* C, long long ldc, T* S, long long lds, int mode, double add_diag,
+                      hipStream_t st) {
+    symmetrize_kernel<T><<<grid_for((long long)n * n), kThreads, 0, st>>>(n, C, ldc, S, lds, mode, add_diag);
+    return hipGetLastError();
+}
+template hipError_t symmetrize<double>(int, const double*, long long, double*, long long, int, double, hipStream_t);
+template hipError_t symmetrize<float>(int, const float*, long long, float*, long long, int, double, hipStream_t);
+
+template <class S, class D>
+hipError_t convert(int m, int n, const S* X, long long ldx, D* Y, long long ldy, double s, hipStream_t st) {
+    convert_kernel<S, D><<<grid_for((long long)m * n), kThreads, 0, st>>>(m, n, X, ldx, Y, ldy, s);
+    return hipGetLastError();
+}
+template hipError_t convert<double, float>(int, int, const double*, long long, float*, long long, double,
+                                           hipStream_t);
+template hipError_t convert<float, double>(int, int, const float*, long long, double*, long long, double,
+                                           hipStream_t);
 
 hipError_t frob2(int m, int n, const double* X, long long ldx, const double* Y, long long ldy, double* part,
                  double* out, hipStream_t st) {

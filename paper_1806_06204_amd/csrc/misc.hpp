@@ -16,14 +16,22 @@ hipError_t scale_copy(int m, int n, const double* A, long long lda, double* X, l
                       int* nonfinite_flag, hipStream_t st);
 hipError_t broadcast_copy(int m, int n, const double* X, long long ldx, double* Y, long long ldy, long long sy,
                           int batch, hipStream_t st);
-hipError_t shift_copy(int n, const double* G, long long ldg, double* Z, long long ldz, long long sz,
-                      const ShiftArgs& sh, hipStream_t st);
-hipError_t fill_matrix(int m, int n, double* Z, long long ldz, long long sz, int batch, double diag, double off,
-                       hipStream_t st);
-hipError_t zero_strict_lower(int n, double* Z, long long ldz, long long sz, int batch, hipStream_t st);
-// mode 0: S = (C + C^T)/2;  mode 1: S = mirror of the upper triangle of C, plus add_diag * I.
-hipError_t symmetrize(int n, const double* C, long long ldc, double* S, long long lds, int mode, double add_diag,
+// The next four exist for T = double and T = float.
+template <class T>
+hipError_t shift_copy(int n, const T* G, long long ldg, T* Z, long long ldz, long long sz, const ShiftArgs& sh,
                       hipStream_t st);
+template <class T>
+hipError_t fill_matrix(int m, int n, T* Z, long long ldz, long long sz, int batch, double diag, double off,
+                       hipStream_t st);
+template <class T>
+hipError_t zero_strict_lower(int n, T* Z, long long ldz, long long sz, int batch, hipStream_t st);
+// mode 0: S = (C + C^T)/2;  mode 1: S = mirror of the upper triangle of C, plus add_diag * I.
+template <class T>
+hipError_t symmetrize(int n, const T* C, long long ldc, T* S, long long lds, int mode, double add_diag,
+                      hipStream_t st);
+// Y = s * X, FP64 -> FP32 or FP32 -> FP64 (m x n).
+template <class S, class D>
+hipError_t convert(int m, int n, const S* X, long long ldx, D* Y, long long ldy, double s, hipStream_t st);
 // out[0] = ||X - Y||_F^2 (0 if Y null), out[1] = ||X||_F^2.  part: >= 2048 doubles.
 hipError_t frob2(int m, int n, const double* X, long long ldx, const double* Y, long long ldy, double* part,
                  double* out, hipStream_t st);
@@ -37,14 +45,18 @@ hipError_t fill_vector(int n, double* v, double val, hipStream_t st);
 hipError_t norm1_upper(int n, const double* R, long long ldr, double* colsum, double* out, hipStream_t st);
 
 // --- chol.hip -------------------------------------------------------------
+// Both exist for T = double and T = float.
 // Batched upper Cholesky Z_b = R_b^T R_b in place (strict lower part zeroed).
 // info_dev[b] (int, device) receives 0 or the 1-based column of the first
-// non-positive pivot.  work: >= batch * 64 * 64 doubles.
-hipError_t potrf_batched(int n, double* Z, long long ldz, long long sz, int batch, int* info_dev, double* work,
+// non-positive pivot.  work: >= batch * 64 * 64 elements.
+template <class T>
+hipError_t potrf_batched(int n, T* Z, long long ldz, long long sz, int batch, int* info_dev, T* work,
                          hipStream_t st);
 // Batched inverse of upper-triangular R_b into Rinv_b (strict lower part zero).
-hipError_t trtri_batched(int n, const double* R, long long ldr, long long sr, double* Rinv, long long ldi,
-                         long long si, int batch, double* work, long long work_elems, hipStream_t st);
+// work: work_elems elements (n^2 batch / 2 + 64^2 batch suffices).
+template <class T>
+hipError_t trtri_batched(int n, const T* R, long long ldr, long long sr, T* Rinv, long long ldi, long long si,
+                         int batch, T* work, long long work_elems, hipStream_t st);
 
 // --- qr.hip ---------------------------------------------------------------
 constexpr int kPanelNB = 64;

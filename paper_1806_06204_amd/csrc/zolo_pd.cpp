@@ -59,15 +59,23 @@ struct Arena {
     }
 };
 
+// Buffers of one Cholesky-type step in precision T.
+template <class T>
+struct CholBufs {
+    T *X, *Xn, *G, *F, *Z, *D, *trtri, *potrf;
+};
+
 struct Work {
     double *X, *Xn, *Y, *D, *G, *F, *trtri, *potrf, *part, *scal, *vec_v, *vec_u, *vec_w, *lam;
     int* iflags;  // [0] nonfinite, [1] panel error, [2..] potrf info per j
     QrWork qr;
+    CholBufs<float> s;  // FP32 copies for the mixed schedule (null unless requested)
     size_t bytes;
 };
 
-// Lay out (or size, if base == nullptr) the workspace for m x n and degree rmax.
-Work layout(char* base, int m, int n, int rmax, int panel_coresident) {
+// Lay out (or size, if base == nullptr) the workspace for m x n and degree
+// rmax; `mixed` adds the FP32 buffers of the mixed precision schedule.
+Work layout(char* base, int m, int n, int rmax, int panel_coresident, bool mixed = false) {
     Arena ar{base};
     const size_t mn = (size_t)m * n, nn = (size_t)n * n;
     const int npanels = (n + kPanelNB - 1) / kPanelNB;
@@ -96,6 +104,17 @@ Work layout(char* base, int m, int n, int rmax, int panel_coresident) {
     w.qr.counters = ar.take<unsigned>((size_t)rmax * npanels);
     w.qr.error_flag = w.iflags + 1;
     w.qr.max_coresident = panel_coresident;
+    w.s = CholBufs<float>{};
+    if (mixed) {
+        w.s.X = ar.take<float>(mn);
+        w.s.Xn = ar.take<float>(mn);
+        w.s.G = ar.take<float>(nn);
+        w.s.F = ar.take<float>(nn);
+        w.s.Z = ar.take<float>(nn * rmax);
+        w.s.D = ar.take<float>(nn * rmax);
+        w.s.trtri = ar.take<float>(nn * rmax / 2 + (size_t)64 * 64 * rmax + 64);
+        w.s.potrf = ar.take<float>((size_t)64 * 64 * rmax);
+    }
     w.bytes = ar.off + 256;
     return w;
 }
@@ -138,8 +157,9 @@ int readback(zolo_handle h, const void* dev, size_t bytes) {
 }
 
 // G = X^T X (upper tiles; symmetric result in the upper triangle).
-hipError_t gram(int m, int n, const double* X, long long ldx, double* G, hipStream_t st) {
-    GemmDesc g;
+template <class T>
+hipError_t gram(int m, int n, const T* X, long long ldx, T* G, hipStream_t st) {
+    GemmDescT<T> g;
     g.m = n; g.n = n; g.k = m; g.transa = 1;
     g.A = X; g.lda = ldx; g.B = X; g.ldb = ldx;
     g.C = G; g.ldc = n;
@@ -154,43 +174,64 @@ struct StepCtx {
     double flops_exec = 0.0;
 };
 
-// One Cholesky-type step X -> Xn.  Returns 0, ZOLO_BREAKDOWN, or an error.
-int chol_step(StepCtx& cx, const Coeffs& co, bool g_valid) {
+// One Cholesky-type step b.X -> b.Xn in precision T.  Returns 0,
+// ZOLO_BREAKDOWN, or an error.  g_valid: b.G already holds X^T X.
+template <class T>
+int chol_core(StepCtx& cx, const Coeffs& co, const CholBufs<T>& b, bool g_valid) {
     const Work& w = *cx.w;
     const int m = cx.m, n = cx.n, r = co.r;
     hipStream_t st = cx.h->stream;
     const long long nn = (long long)n * n;
     if (!g_valid) {
-        HIPCHECK(gram(m, n, w.X, m, w.G, st));
+        HIPCHECK(gram<T>(m, n, b.X, m, b.G, st));
         cx.flops_exec += (double)m * n * n;
     }
     ShiftArgs sh;
     sh.batch = r;
     for (int j = 0; j < r; ++j) sh.shift[j] = co.c[2 * j];
-    HIPCHECK(shift_copy(n, w.G, n, w.Y, n, nn, sh, st));
-    HIPCHECK(potrf_batched(n, w.Y, n, nn, r, w.iflags + 2, w.potrf, st));
+    HIPCHECK(shift_copy<T>(n, b.G, n, b.Z, n, nn, sh, st));
+    HIPCHECK(potrf_batched<T>(n, b.Z, n, nn, r, w.iflags + 2, b.potrf, st));
     int rc = readback(cx.h, w.iflags + 2, sizeof(int) * r);
     if (rc) return rc;
     for (int j = 0; j < r; ++j)
         if (reinterpret_cast<int*>(cx.h->host)[j] != 0) return ZOLO_BREAKDOWN;
-    HIPCHECK(trtri_batched(n, w.Y, n, nn, w.D, n, nn, r, w.trtri, (long long)nn * r / 2 + 64 * 64 * r, st));
+    HIPCHECK(trtri_batched<T>(n, b.Z, n, nn, b.D, n, nn, r, b.trtri, (long long)nn * r / 2 + 64 * 64 * r, st));
     // F = sum_j a_j R_j^{-1} R_j^{-T} (upper tiles), then mirror and add I.
-    GemmDesc f;
+    GemmDescT<T> f;
     f.m = n; f.n = n; f.k = n; f.transb = 1;
-    f.A = w.D; f.lda = n; f.strideA = nn;
-    f.B = w.D; f.ldb = n; f.strideB = nn;
-    f.C = w.G; f.ldc = n;
+    f.A = b.D; f.lda = n; f.strideA = nn;
+    f.B = b.D; f.ldb = n; f.strideB = nn;
+    f.C = b.G; f.ldc = n;
     f.batch = r; f.reduce = 1; f.nalpha = r;
     for (int j = 0; j < r; ++j) f.alphas[j] = co.a[j];
     f.flags = kAUpper | kBLower | kCUpperTiles | kCStoreUpper;
     HIPCHECK(gemm(f, st));
-    HIPCHECK(symmetrize(n, w.G, n, w.F, n, 1, 1.0, st));
-    GemmDesc x;
+    HIPCHECK(symmetrize<T>(n, b.G, n, b.F, n, 1, 1.0, st));
+    GemmDescT<T> x;
     x.m = m; x.n = n; x.k = n;
-    x.A = w.X; x.lda = m; x.B = w.F; x.ldb = n;
-    x.C = w.Xn; x.ldc = m; x.alpha = co.mhat;
+    x.A = b.X; x.lda = m; x.B = b.F; x.ldb = n;
+    x.C = b.Xn; x.ldc = m; x.alpha = co.mhat;
     HIPCHECK(gemm(x, st));
     cx.flops_exec += r * (double)n * n * n + 2.0 * m * (double)n * n;
+    return 0;
+}
+
+// FP64 Cholesky-type step on the main buffers (Z_j live in the QR stack buffer).
+int chol_step(StepCtx& cx, const Coeffs& co, bool g_valid) {
+    const Work& w = *cx.w;
+    return chol_core<double>(cx, co, CholBufs<double>{w.X, w.Xn, w.G, w.F, w.Y, w.D, w.trtri, w.potrf}, g_valid);
+}
+
+// The same step in FP32 (mixed schedule): X is rounded to FP32, the step runs
+// on the FP32 matrix cores and its result is widened back into Xn.
+int chol_step_fp32(StepCtx& cx, const Coeffs& co) {
+    const Work& w = *cx.w;
+    const int m = cx.m, n = cx.n;
+    hipStream_t st = cx.h->stream;
+    HIPCHECK((convert<double, float>(m, n, w.X, m, w.s.X, m, 1.0, st)));
+    const int rc = chol_core<float>(cx, co, w.s, false);
+    if (rc) return rc;
+    HIPCHECK((convert<float, double>(m, n, w.s.Xn, m, w.Xn, m, 1.0, st)));
     return 0;
 }
 
@@ -221,7 +262,7 @@ int qr_step(StepCtx& cx, const Coeffs& co) {
 
 bool opts_ok(const zolo_opts& o) {
     return o.max_iter >= 1 && o.max_iter <= ZOLO_MAX_ITER && (o.stop_rule == 0 || o.stop_rule == 1) &&
-           o.tau > 0.0 && o.chol_switch >= 1.0 && o.qr_variant == 0 && o.precision == 0;
+           o.tau > 0.0 && o.chol_switch >= 1.0 && o.qr_variant == 0 && (o.precision == 0 || o.precision == 1);
 }
 
 }  // namespace
@@ -320,14 +361,15 @@ int zolo_pd(zolo_handle h, int m, int n, const double* A, int lda, double alpha,
     inf.orth_err = -1.0;
     Timer whole, stage;
     const int rmax = r >= 1 ? r : kMaxR;
-    Work w = layout(nullptr, m, n, rmax, h->panel_coresident);
+    const bool mixed = opts.precision == 1;
+    Work w = layout(nullptr, m, n, rmax, h->panel_coresident, mixed);
     int rc = ensure(h, w.bytes);
     if (rc) {
         inf.status = rc;
         if (info) *info = inf;
         return rc;
     }
-    w = layout(h->arena, m, n, rmax, h->panel_coresident);
+    w = layout(h->arena, m, n, rmax, h->panel_coresident, mixed);
     hipStream_t st = h->stream;
     const long long mn = (long long)m * n;
     int* hi = reinterpret_cast<int*>(h->host);
@@ -400,11 +442,16 @@ int zolo_pd(zolo_handle h, int m, int n, const double* A, int lda, double alpha,
         compute_coeffs(l, r, &co);
         inf.l_seq[it] = l;
         char kind = co.kappa_z > opts.chol_switch ? 'Q' : 'C';
+        // Mixed schedule: a Cholesky-type step that is not predicted to be
+        // the last one runs in FP32; the last step, every QR-type step and H
+        // stay in FP64.
+        char prec = (mixed && kind == 'C' && co.l_next < kConverged) ? 's' : 'd';
         if (kind == 'C') {
-            rc = chol_step(cx, co, g_valid);
+            rc = prec == 's' ? chol_step_fp32(cx, co) : chol_step(cx, co, g_valid);
             if (rc == ZOLO_BREAKDOWN) {
                 ++inf.chol_fallbacks;
                 kind = 'Q';
+                prec = 'd';
             } else if (rc) {
                 return finish(rc);
             }
@@ -418,6 +465,7 @@ int zolo_pd(zolo_handle h, int m, int n, const double* A, int lda, double alpha,
         }
         g_valid = false;
         inf.kind[it] = kind;
+        inf.prec[it] = prec;
         inf.iters = it + 1;
         inf.flops_paper += kind == 'Q' ? 5.0 * r * m * (double)n * n
                                        : m * (double)n * n + r * ((double)n * n * n / 3.0 + 2.0 * m * (double)n * n);
@@ -457,6 +505,7 @@ int zolo_pd(zolo_handle h, int m, int n, const double* A, int lda, double alpha,
         }
     }
     inf.kind[inf.iters] = 0;
+    inf.prec[inf.iters] = 0;
 
     // Step 5: Qp = X, H = (Qp^T A + (Qp^T A)^T) / 2.
     HIPCHECK(hipMemcpy2DAsync(Qp, sizeof(double) * ldq, w.X, sizeof(double) * m, sizeof(double) * m, n,
@@ -517,7 +566,8 @@ int zolo_pd_batched(zolo_handle h, int count, const int* m, const int* n, const 
         if (!H[i]) return -12;
         if (ldh[i] < n[i]) return -13;
         const int rmax = (r && r[i] >= 1) ? r[i] : kMaxR;
-        need = std::max(need, layout(nullptr, m[i], n[i], rmax, h->panel_coresident).bytes);
+        need = std::max(need, layout(nullptr, m[i], n[i], rmax, h->panel_coresident,
+                                     opts && opts->precision == 1).bytes);
     }
     if (int rc = ensure(h, need)) return rc;
     int worst = 0;

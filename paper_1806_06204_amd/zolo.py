@@ -31,7 +31,8 @@ class ZoloOpts(ctypes.Structure):
 
 class ZoloInfo(ctypes.Structure):
     _fields_ = [("status", c_int), ("iters", c_int), ("r_used", c_int), ("chol_fallbacks", c_int),
-                ("kind", ctypes.c_char * (MAX_ITER + 1)), ("alpha", c_double), ("l0", c_double),
+                ("kind", ctypes.c_char * (MAX_ITER + 1)), ("prec", ctypes.c_char * (MAX_ITER + 1)),
+                ("alpha", c_double), ("l0", c_double),
                 ("l_seq", c_double * MAX_ITER), ("orth_check", c_double), ("t_stage", c_double * 8),
                 ("flops_exec", c_double), ("flops_paper", c_double), ("bwd_err", c_double),
                 ("orth_err", c_double)]
@@ -39,7 +40,8 @@ class ZoloInfo(ctypes.Structure):
     def as_dict(self):
         it = self.iters
         return {"status": self.status, "iters": it, "r": self.r_used, "chol_fallbacks": self.chol_fallbacks,
-                "kinds": list(self.kind.decode()), "alpha": self.alpha, "l0": self.l0,
+                "kinds": list(self.kind.decode()), "prec": self.prec.decode(), "alpha": self.alpha,
+                "l0": self.l0,
                 "ls": list(self.l_seq[:it]), "orth_check": self.orth_check,
                 "t_stage_ms": list(self.t_stage), "flops_exec": self.flops_exec,
                 "flops_paper": self.flops_paper, "bwd_err": self.bwd_err, "orth_err": self.orth_err}
@@ -49,8 +51,8 @@ _lib = None
 
 EXPORTS = ["zolo_default_opts", "zolo_create", "zolo_set_stream", "zolo_destroy", "zolo_coeffs", "zolo_pd",
            "zolo_pd_batched", "zolo_svd", "zolo_dgemm", "zolo_dpotrf_batched", "zolo_dtrtri_batched",
-           "zolo_structured_qr_batched", "zolo_stats_enable", "zolo_stats_reset", "zolo_stats_get",
-           "zolo_stats_count"]
+           "zolo_sgemm", "zolo_spotrf_batched", "zolo_strtri_batched", "zolo_structured_qr_batched",
+           "zolo_stats_enable", "zolo_stats_reset", "zolo_stats_get", "zolo_stats_count"]
 
 
 def load():
@@ -80,8 +82,12 @@ def load():
                              ctypes.POINTER(ZoloOpts), ctypes.POINTER(ZoloInfo)]
     lib.zolo_dgemm.argtypes = [P, c_int, c_int, c_int, c_int, c_int, c_double, P, c_int, c_longlong, P, c_int,
                                c_longlong, c_double, P, c_int, c_longlong, c_int]
+    lib.zolo_sgemm.argtypes = [P, c_int, c_int, c_int, c_int, c_int, ctypes.c_float, P, c_int, c_longlong, P,
+                               c_int, c_longlong, ctypes.c_float, P, c_int, c_longlong, c_int]
     lib.zolo_dpotrf_batched.argtypes = [P, c_int, P, c_int, c_longlong, c_int, ctypes.POINTER(c_int)]
+    lib.zolo_spotrf_batched.argtypes = [P, c_int, P, c_int, c_longlong, c_int, ctypes.POINTER(c_int)]
     lib.zolo_dtrtri_batched.argtypes = [P, c_int, P, c_int, c_longlong, P, c_int, c_longlong, c_int]
+    lib.zolo_strtri_batched.argtypes = [P, c_int, P, c_int, c_longlong, P, c_int, c_longlong, c_int]
     lib.zolo_structured_qr_batched.argtypes = [P, c_int, c_int, D, P, c_int, c_longlong, P, c_int, c_longlong,
                                                c_int, c_int]  # M, ldm, strideM, R, ldr, strideR, batch, form_q
     lib.zolo_stats_enable.argtypes = [c_int]
@@ -271,45 +277,57 @@ class Zolo:
         """(batch, rows, cols) tensor -> contiguous buffer (batch, cols, rows)."""
         return X.transpose(-1, -2).contiguous()
 
-    def gemm(self, A, B, C=None, transa=False, transb=False, alpha=1.0, beta=0.0):
-        """Batched C = alpha op(A) op(B) + beta C on (batch, rows, cols) stacks."""
+    def _prefix(self, X):
         torch = _torch()
-        Ab, Bb = self._stack_cm(A), self._stack_cm(B)
+        if X.dtype == torch.float64:
+            return "d"
+        if X.dtype == torch.float32:
+            return "s"
+        raise TypeError("building blocks take float64 (FP64) or float32 (FP32) stacks")
+
+    def gemm(self, A, B, C=None, transa=False, transb=False, alpha=1.0, beta=0.0):
+        """Batched C = alpha op(A) op(B) + beta C on (batch, rows, cols) stacks
+        (float64 -> zolo_dgemm, float32 -> zolo_sgemm)."""
+        torch = _torch()
+        p = self._prefix(A)
+        Ab, Bb = self._stack_cm(A), self._stack_cm(B.to(A.dtype))
         batch = A.shape[0]
         m = A.shape[2] if transa else A.shape[1]
         k = A.shape[1] if transa else A.shape[2]
         n = B.shape[1] if transb else B.shape[2]
         if C is None:
-            Cb = torch.zeros((batch, n, m), dtype=torch.float64, device=A.device)
+            Cb = torch.zeros((batch, n, m), dtype=A.dtype, device=A.device)
         else:
-            Cb = self._stack_cm(C)
-        rc = self.lib.zolo_dgemm(self.h, int(transa), int(transb), m, n, k, float(alpha),
-                                 c_void_p(Ab.data_ptr()), A.shape[1], A.shape[1] * A.shape[2],
-                                 c_void_p(Bb.data_ptr()), B.shape[1], B.shape[1] * B.shape[2], float(beta),
-                                 c_void_p(Cb.data_ptr()), m, m * n, batch)
+            Cb = self._stack_cm(C.to(A.dtype))
+        rc = getattr(self.lib, f"zolo_{p}gemm")(self.h, int(transa), int(transb), m, n, k, float(alpha),
+                                                c_void_p(Ab.data_ptr()), A.shape[1], A.shape[1] * A.shape[2],
+                                                c_void_p(Bb.data_ptr()), B.shape[1], B.shape[1] * B.shape[2],
+                                                float(beta), c_void_p(Cb.data_ptr()), m, m * n, batch)
         if rc:
-            _raise(rc, "zolo_dgemm")
+            _raise(rc, f"zolo_{p}gemm")
         return Cb.transpose(-1, -2)
 
     def potrf(self, Z):
         """Batched upper Cholesky of a (batch, n, n) stack: returns (R, info list)."""
+        p = self._prefix(Z)
         Zb = self._stack_cm(Z)
         batch, n = Z.shape[0], Z.shape[1]
         info = (c_int * batch)()
-        rc = self.lib.zolo_dpotrf_batched(self.h, n, c_void_p(Zb.data_ptr()), n, n * n, batch, info)
+        rc = getattr(self.lib, f"zolo_{p}potrf_batched")(self.h, n, c_void_p(Zb.data_ptr()), n, n * n, batch, info)
         if rc not in (0, 6):
-            _raise(rc, "zolo_dpotrf_batched")
+            _raise(rc, f"zolo_{p}potrf_batched")
         return Zb.transpose(-1, -2), list(info)
 
     def trtri(self, R):
         torch = _torch()
+        p = self._prefix(R)
         Rb = self._stack_cm(R)
         batch, n = R.shape[0], R.shape[1]
         Ib = torch.empty_like(Rb)
-        rc = self.lib.zolo_dtrtri_batched(self.h, n, c_void_p(Rb.data_ptr()), n, n * n,
-                                          c_void_p(Ib.data_ptr()), n, n * n, batch)
+        rc = getattr(self.lib, f"zolo_{p}trtri_batched")(self.h, n, c_void_p(Rb.data_ptr()), n, n * n,
+                                                         c_void_p(Ib.data_ptr()), n, n * n, batch)
         if rc:
-            _raise(rc, "zolo_dtrtri_batched")
+            _raise(rc, f"zolo_{p}trtri_batched")
         return Ib.transpose(-1, -2)
 
     def structured_qr(self, Y, pivots=None, form_q=True):

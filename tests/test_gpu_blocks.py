@@ -58,6 +58,63 @@ def test_gemm_large(z):
     assert np.abs(out - A @ B).max() <= 1e-12 * 777
 
 
+# --- FP32 building blocks (the FP32 steps of the mixed schedule) ----------
+# References are FP64 products of the same FP32 inputs; the bound is the
+# usual k u |A||B| with u = 2^-24, taken elementwise.
+U32 = 2.0 ** -24
+
+
+@pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
+@pytest.mark.parametrize("m,n,k", [(16, 16, 4), (37, 53, 29), (257, 129, 65), (300, 260, 400)])
+def test_sgemm(z, ta, tb, m, n, k):
+    import torch
+    rng = np.random.default_rng(m * 5 + n + k + 3 * ta + 7 * tb)
+    A = rng.standard_normal((2, k, m) if ta else (2, m, k)).astype(np.float32)
+    B = rng.standard_normal((2, n, k) if tb else (2, k, n)).astype(np.float32)
+    C = rng.standard_normal((2, m, n)).astype(np.float32)
+    out = z.gemm(dev(A), dev(B), dev(C), transa=ta, transb=tb, alpha=0.5, beta=2.0)
+    assert out.dtype == torch.float32
+    out = out.cpu().numpy().astype(np.float64)
+    opA = np.swapaxes(A, 1, 2).astype(np.float64) if ta else A.astype(np.float64)
+    opB = np.swapaxes(B, 1, 2).astype(np.float64) if tb else B.astype(np.float64)
+    ref = 0.5 * opA @ opB + 2.0 * C
+    bound = (k + 2) * U32 * (0.5 * np.abs(opA) @ np.abs(opB) + 2.0 * np.abs(C)) + 1e-30
+    assert np.all(np.abs(out - ref) <= bound)
+
+
+def test_sgemm_mfma_layout_identity(z):
+    # Exact in FP32: a product with a permutation matrix moves every entry to
+    # its own (row, column), so any mix-up of the FP32 accumulator rows shows.
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((1, 256, 128)).astype(np.float32)
+    P = np.eye(128, dtype=np.float32)[rng.permutation(128)][None]
+    out = z.gemm(dev(A), dev(P)).cpu().numpy()
+    assert np.array_equal(out, A @ P)
+    out_t = z.gemm(dev(P), dev(np.swapaxes(A, 1, 2).copy()), transa=True).cpu().numpy()
+    assert np.array_equal(out_t, np.swapaxes(P, 1, 2) @ np.swapaxes(A, 1, 2))
+
+
+@pytest.mark.parametrize("n", [1, 64, 200])
+def test_spotrf_strtri(z, n):
+    # Well conditioned (kappa <= 100, the Cholesky-step regime) FP32 Z_j.
+    rng = np.random.default_rng(n + 7)
+    Zs = []
+    for b in range(3):
+        Q = np.linalg.qr(rng.standard_normal((n, n)))[0]
+        Zs.append((Q * np.linspace(1.0, 100.0, n)) @ Q.T)
+    Zs = np.stack(Zs).astype(np.float32)
+    R, info = z.potrf(dev(Zs))
+    assert info == [0, 0, 0]
+    Ri = z.trtri(R).cpu().numpy().astype(np.float64)
+    R = R.cpu().numpy().astype(np.float64)
+    for b in range(3):
+        Z64 = Zs[b].astype(np.float64)
+        assert np.allclose(np.tril(R[b], -1), 0.0) and np.allclose(np.tril(Ri[b], -1), 0.0)
+        # backward error of the factor and residual of the inverse, FP32 sized
+        assert np.linalg.norm(R[b].T @ R[b] - Z64) <= 8 * n * U32 * np.linalg.norm(Z64)
+        assert np.abs(Ri[b] @ R[b] - np.eye(n)).max() <= 8 * n * U32 * 10.0
+
+
 @pytest.mark.parametrize("n", [1, 64, 200])
 def test_potrf(z, n):
     rng = np.random.default_rng(n)

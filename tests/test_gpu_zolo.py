@@ -185,3 +185,37 @@ def test_batched_mid_sizes(z):
         assert oz.backward_error(A, Q, H) <= BAR and oz.orthogonality(Q) <= BAR
         Hx = (V * sig) @ V.T
         assert np.linalg.norm(H - Hx) / np.linalg.norm(Hx) <= 1e-12
+
+
+def test_mixed_schedule_fp32_middle_step(z):
+    # 256 x 128, kappa = 1e8, r = 3: schedule Q, C, C; the middle Cholesky-type
+    # step is the only one the mixed schedule runs in FP32.  Orthogonality is
+    # restored by the final FP64 step, but the backward error stays at the
+    # size of the FP32 perturbation (the polar factor of the perturbed iterate
+    # is what the remaining steps converge to).
+    cfg = W.config_small()
+    A = cfg["A"]
+    Ad = dev(A)
+    Q64, H64, i64 = z.pd(Ad, alpha=1.0, l=cfg["l"], r=3)
+    Qm, Hm, im = z.pd(Ad, alpha=1.0, l=cfg["l"], r=3, precision=1)
+    assert "".join(i64["kinds"]) == "QCC" and i64["prec"] == "ddd"
+    assert "".join(im["kinds"]) == "QCC" and im["prec"] == "dsd"
+    assert im["status"] == 0
+    Qm, Hm = Qm.cpu().numpy(), Hm.cpu().numpy()
+    assert oz.orthogonality(Qm) <= BAR
+    bwd = oz.backward_error(A, Qm, Hm)
+    assert 1e-11 < bwd <= 1e-5
+    Ho = oz.zolo_pd(A, 1.0, cfg["l"], 3)[1]
+    assert np.linalg.norm(Hm - Ho) / np.linalg.norm(Ho) <= 1e-5
+
+
+def test_mixed_schedule_without_middle_step_is_fp64(z):
+    # kappa = 1e8 with the policy degree (schedule Q, C): no step is predicted
+    # to be followed by another Cholesky step, so mixed equals FP64 exactly.
+    cfg = W.config_small()
+    Ad = dev(cfg["A"])
+    Q64, H64, i64 = z.pd(Ad, alpha=1.0, l=cfg["l"], r=6)
+    Qm, Hm, im = z.pd(Ad, alpha=1.0, l=cfg["l"], r=6, precision=1)
+    assert "".join(im["kinds"]) == "".join(i64["kinds"]) and set(im["prec"]) == {"d"}
+    assert np.array_equal(Q64.cpu().numpy(), Qm.cpu().numpy())
+    assert np.array_equal(H64.cpu().numpy(), Hm.cpu().numpy())
