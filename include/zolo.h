@@ -62,7 +62,9 @@ typedef struct {
     int max_iter;        /* iteration limit (default 10, at most ZOLO_MAX_ITER) */
     int stop_rule;       /* 0 verified (default): once the predicted l reaches
                             1 - 1e-15, stop when ||X^T X - I||_F / sqrt(n) <= tau,
-                            else continue with l = sqrt(1 - sqrt(n) d);
+                            else continue with l = sqrt(1 - sqrt(n) d), or, if
+                            sqrt(n) d >= 1, with the condition estimate of
+                            the current X;
                             1 paper: ||X_new - X_old||_F / ||X_new||_F <= eps^(1/(2r+1))
                             (Algorithm 1 step 4(d), Algorithm 3 step 4(e)) */
     double tau;          /* verified-stop threshold (default 5e-14) */
@@ -84,7 +86,17 @@ typedef struct {
                             FP32.  info->prec says which steps did. */
     int compute_errors;  /* 1: fill info->bwd_err and info->orth_err (costs two
                             extra GEMMs); 0 (default): leave them at -1 */
-    int reserved[9];
+    int l_source;        /* how l is found when the caller passes l <= 0:
+                            0 (default) condition estimate from a QR of X0;
+                            1 the learned estimator installed with
+                            zolo_set_estimator (zolo_learn.h): 39 features of
+                            a 32-column sketch of X0 into a small network that
+                            also gives r when r <= 0.  Without an installed
+                            estimator, or when its output is not finite, the
+                            condition estimate is used.  Either way the
+                            verified stop rule judges the result: an l above
+                            sigma_min costs iterations, not accuracy. */
+    int reserved[8];
 } zolo_opts;
 
 /* Per-call report. */
@@ -93,6 +105,10 @@ typedef struct {
     int iters;             /* iterations taken */
     int r_used;            /* Zolotarev degree r */
     int chol_fallbacks;    /* Cholesky-type steps redone as QR-type */
+    int l_from;            /* 0 l given, 1 condition estimate, 2 learned */
+    int l_reestimates;     /* verified stop: times sqrt(n) d >= 1 voided the
+                              bound from d (l was above sigma_min) and l was
+                              re-estimated from the current X */
     char kind[ZOLO_MAX_ITER + 1];  /* 'Q' or 'C' per iteration, NUL-terminated */
     char prec[ZOLO_MAX_ITER + 1];  /* 'd' (FP64) or 's' (FP32) per iteration */
     double alpha;          /* scaling alpha >= sigma_max(A) used, X0 = A / alpha */

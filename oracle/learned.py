@@ -18,10 +18,13 @@ G1  Counter-based generator: SplitMix64 (Steele, Lea & Flood, "Fast
     Gaussian number k: sqrt(-2 ln u_{2k}) cos(2 pi u_{2k+1}) (Box-Muller,
     cosine branch).
 G2  Sketch: Omega (n x 32) with Omega[i, j] = Gaussian number i + j n of the
-    stream; Y = X0 Omega; s_1 >= ... >= s_32 are the singular values of Y.
+    stream; Y = X0 Omega; s_1 >= ... >= s_32 are the square roots of the
+    eigenvalues of the Gram matrix Y^T Y.  Through the Gram matrix an s_i
+    carries an absolute error of about eps s_1^2 / s_i, so ratios below 1e-6
+    are rounding noise in any implementation; G3 floors them there.
 G3  Features (39), norms clamped below at 1e-20 before each logarithm:
       f0        log10 s_1
-      f1..f31   max(log10(s_{i+1} / s_1), -20)
+      f1..f31   max(log10(s_{i+1} / s_1), -6)
       f32, f33  mean and population std of log10 ||X0 e_j|| over the n columns
       f34, f35  the same over the m rows
       f36, f37  log10 n, log10(m / n)
@@ -64,6 +67,7 @@ NF = 39          # features
 NH = 64          # hidden width
 NO = 2           # outputs
 NS = 32          # sketch columns
+LOG_FLOOR = -6.0  # floor of the normalised log sketch singular values (G2)
 N_PARAMS = 2 * NF + NH * NF + NH + NH * NH + NH + NO * NH + NO
 N_STATS = 2 * NF  # mu and sd lead the layout and are not trained
 
@@ -113,7 +117,7 @@ def features_from(svals, colnorms, rownorms, m, n, frob):
     s = np.sort(np.maximum(np.asarray(svals, dtype=np.float64), 0.0))[::-1]
     f = np.empty(NF)
     f[0] = _log10c(s[0])
-    f[1:NS] = np.maximum(_log10c(s[1:]) - _log10c(s[0]), -20.0)
+    f[1:NS] = np.maximum(_log10c(s[1:]) - _log10c(s[0]), LOG_FLOOR)
     lc, lr = _log10c(np.asarray(colnorms)), _log10c(np.asarray(rownorms))
     f[32], f[33] = lc.mean(), lc.std()
     f[34], f[35] = lr.mean(), lr.std()

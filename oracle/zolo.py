@@ -29,8 +29,10 @@ R8  stop rule.  Paper mode: ||X_new - X_old||_F / ||X_new||_F <= eps^(1/(2r+1))
     with eps = 2^-52 (Algorithm 1 step 4(d), Algorithm 3 step 4(e)).
     Verified mode (default): once the predicted l reaches 1 - 1e-15 compute
     d = ||X^T X - I||_F / sqrt(n); stop if d <= tau, else continue with
-    l = sqrt(1 - sqrt(n) d) (a lower bound on sigma_min when sqrt(n) d < 1),
-    or l_pred / 10 otherwise.
+    l = sqrt(1 - sqrt(n) d) (a lower bound on sigma_min when sqrt(n) d < 1).
+    When sqrt(n) d >= 1 that bound is void (l was above sigma_min, so some
+    singular values are still far from 1) and l is re-estimated by R2 on the
+    current X, which is a bound again.
 R9  "return to Step 1 with A <- X2": continue the loop with X and l updated,
     as Algorithm 3 step 4(e) states.
 """
@@ -132,8 +134,8 @@ def zolo_pd(A, alpha=None, l=None, r=None, *, stop="verified", tau=5e-14,
 
     Returns (Qp, H, info).  info holds: status (0 converged, 1 not converged
     within max_iter), iters, kinds (one 'Q'/'C' per step), ls (l before each
-    step), r, alpha, l0, chol_fallbacks and, if record, the iterates X_k
-    (X_0 = A / alpha first)."""
+    step), r, alpha, l0, chol_fallbacks, l_reestimates (R8) and, if record,
+    the iterates X_k (X_0 = A / alpha first)."""
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
     if m < n:
@@ -152,7 +154,7 @@ def zolo_pd(A, alpha=None, l=None, r=None, *, stop="verified", tau=5e-14,
     if r is None:
         r = zc.choose_r(l)
     info = {"status": 1, "iters": 0, "kinds": [], "ls": [], "r": int(r),
-            "alpha": float(alpha), "l0": l0, "chol_fallbacks": 0,
+            "alpha": float(alpha), "l0": l0, "chol_fallbacks": 0, "l_reestimates": 0,
             "iterates": [X.copy()] if record else None, "orth_checks": []}
     for _ in range(max_iter):
         co = zc.coefficients(l, r)
@@ -186,7 +188,11 @@ def zolo_pd(A, alpha=None, l=None, r=None, *, stop="verified", tau=5e-14,
                     info["status"] = 0
                     break
                 b = math.sqrt(n) * d
-                l = math.sqrt(max(zc.L_MIN ** 2, 1.0 - b)) if b < 1.0 else l_pred / 10.0
+                if b < 1.0:
+                    l = math.sqrt(max(zc.L_MIN ** 2, 1.0 - b))
+                else:
+                    l = min(max(estimate_l(X), zc.L_MIN), 1.0)
+                    info["l_reestimates"] += 1
             else:
                 l = l_pred
     Qp = X

@@ -13,4 +13,5 @@ struct zolo_handle_s {
     size_t arena_bytes = 0;
     double* host = nullptr;  // pinned scalars for read-back
     int panel_coresident = 0;
+    float* est = nullptr;    // learned l/r estimator parameters (zolo_set_estimator)
 };

@@ -32,8 +32,10 @@
 
 #include "../../include/zolo.h"
 #include "../../include/zolo_blocks.h"
+#include "../../include/zolo_learn.h"
 #include "coeffs.hpp"
 #include "handle.hpp"
+#include "learn.hpp"
 #include "misc.hpp"
 
 namespace zolo {
@@ -70,6 +72,8 @@ struct Work {
     int* iflags;  // [0] nonfinite, [1] panel error, [2..] potrf info per j
     QrWork qr;
     CholBufs<float> s;  // FP32 copies for the mixed schedule (null unless requested)
+    double *sk, *feat;  // sketch scratch and the 39 features (learned l)
+    float* mlp;         // network activations for one feature vector
     size_t bytes;
 };
 
@@ -104,6 +108,9 @@ Work layout(char* base, int m, int n, int rmax, int panel_coresident, bool mixed
     w.qr.counters = ar.take<unsigned>((size_t)rmax * npanels);
     w.qr.error_flag = w.iflags + 1;
     w.qr.max_coresident = panel_coresident;
+    w.sk = ar.take<double>(sketch_scratch_elems(m, n));
+    w.feat = ar.take<double>(64);
+    w.mlp = ar.take<float>(kNF + 2 * kNH + 64);
     w.s = CholBufs<float>{};
     if (mixed) {
         w.s.X = ar.take<float>(mn);
@@ -235,6 +242,26 @@ int chol_step_fp32(StepCtx& cx, const Coeffs& co) {
     return 0;
 }
 
+// Condition estimate (the reading used when l is not given): X = Q R by a
+// Householder QR (no identity block), then l = 1 / (sqrt(n) ||R^{-1}||_1),
+// which is <= 1 / ||R^{-1}||_2 = sigma_min(X).  Overwrites Y, D and G.
+int condition_estimate(StepCtx& cx, const double* X, double* l_out) {
+    const Work& w = *cx.w;
+    const int m = cx.m, n = cx.n;
+    const long long mn = (long long)m * n, nn = (long long)n * n;
+    hipStream_t st = cx.h->stream;
+    HIPCHECK(hipMemcpyAsync(w.Y, X, sizeof(double) * mn, hipMemcpyDeviceToDevice, st));
+    HIPCHECK(structured_geqrf(m, 0, n, w.Y, m, mn, 1, w.qr, st));
+    HIPCHECK(assemble_r(n, w.Y, m, mn, 1, w.qr, w.D, n, nn, st));
+    HIPCHECK(trtri_batched(n, w.D, n, nn, w.G, n, nn, 1, w.trtri, nn / 2 + 64 * 64, st));
+    HIPCHECK(norm1_upper(n, w.G, n, w.vec_u, w.scal, st));
+    if (int rc = readback(cx.h, w.scal, sizeof(double))) return rc;
+    const double nrm = cx.h->host[0];
+    *l_out = (std::isfinite(nrm) && nrm > 0.0) ? 1.0 / (std::sqrt((double)n) * nrm) : kLMin;
+    cx.flops_exec += 2.0 * m * (double)n * n + (double)n * n * n / 3.0;
+    return 0;
+}
+
 int qr_step(StepCtx& cx, const Coeffs& co) {
     const Work& w = *cx.w;
     const int m = cx.m, n = cx.n, r = co.r;
@@ -262,7 +289,8 @@ int qr_step(StepCtx& cx, const Coeffs& co) {
 
 bool opts_ok(const zolo_opts& o) {
     return o.max_iter >= 1 && o.max_iter <= ZOLO_MAX_ITER && (o.stop_rule == 0 || o.stop_rule == 1) &&
-           o.tau > 0.0 && o.chol_switch >= 1.0 && o.qr_variant == 0 && (o.precision == 0 || o.precision == 1);
+           o.tau > 0.0 && o.chol_switch >= 1.0 && o.qr_variant == 0 && (o.precision == 0 || o.precision == 1) &&
+           (o.l_source == 0 || o.l_source == 1);
 }
 
 }  // namespace
@@ -318,6 +346,7 @@ int zolo_destroy(zolo_handle h) {
         (void)hipFree(h->arena);
     }
     if (h->host) (void)hipHostFree(h->host);
+    if (h->est) (void)hipFree(h->est);
     delete h;
     return 0;
 }
@@ -386,6 +415,7 @@ int zolo_pd(zolo_handle h, int m, int n, const double* A, int lda, double alpha,
         return status;
     };
 
+    StepCtx cx{h, &w, m, n};
     HIPCHECK(hipMemsetAsync(w.iflags, 0, sizeof(int) * 64, st));
     // Step 1: alpha (upper bound of sigma_max) and X0 = A / alpha.
     if (!(alpha > 0.0)) {
@@ -412,19 +442,24 @@ int zolo_pd(zolo_handle h, int m, int n, const double* A, int lda, double alpha,
     if (hi[0]) return finish(ZOLO_NONFINITE);
 
     // Step 2: l, a lower bound on sigma_min(X0).
+    if (!(l > 0.0) && opts.l_source == 1 && h->est) {
+        // Learned estimate: sketch features of X0 into the installed network.
+        HIPCHECK(sketch_features(m, n, w.X, m, ZOLO_SKETCH_SEED, w.feat, w.sk, st));
+        MlpBufs a{w.mlp, w.mlp + kNF, w.mlp + kNF + kNH, w.mlp + kNF + 2 * kNH};
+        HIPCHECK(mlp_forward(1, h->est, w.feat, nullptr, a, st));
+        HIPCHECK(hipMemcpyAsync(h->host, a.Y, 2 * sizeof(float), hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipStreamSynchronize(st));
+        const float* yo = reinterpret_cast<const float*>(h->host);
+        if (std::isfinite(yo[0]) && std::isfinite(yo[1])) {
+            l = std::pow(10.0, std::min(0.0, std::max(-20.0, (double)yo[0])));
+            if (r < 1) r = std::min(kMaxR, std::max(1, (int)std::lround(yo[1])));
+            inf.l_from = 2;
+        }
+        inf.flops_exec += 2.0 * m * (double)n * kNS + 2.0 * m * (double)kNS * kNS;
+    }
     if (!(l > 0.0)) {
-        // X0 = Q R (Householder, no identity block), then
-        // l = 1 / (sqrt(n) ||R^{-1}||_1) <= 1 / ||R^{-1}||_2 = sigma_min(X0).
-        HIPCHECK(hipMemcpyAsync(w.Y, w.X, sizeof(double) * mn, hipMemcpyDeviceToDevice, st));
-        HIPCHECK(structured_geqrf(m, 0, n, w.Y, m, mn, 1, w.qr, st));
-        HIPCHECK(assemble_r(n, w.Y, m, mn, 1, w.qr, w.D, n, (long long)n * n, st));
-        HIPCHECK(trtri_batched(n, w.D, n, (long long)n * n, w.G, n, (long long)n * n, 1, w.trtri,
-                               (long long)n * n / 2 + 64 * 64, st));
-        HIPCHECK(norm1_upper(n, w.G, n, w.vec_u, w.scal, st));
-        if ((rc = readback(h, w.scal, sizeof(double)))) return finish(rc);
-        const double nrm = h->host[0];
-        l = (std::isfinite(nrm) && nrm > 0.0) ? 1.0 / (std::sqrt((double)n) * nrm) : kLMin;
-        inf.flops_exec += 2.0 * m * (double)n * n + (double)n * n * n / 3.0;
+        inf.l_from = 1;
+        if ((rc = condition_estimate(cx, w.X, &l))) return finish(rc);
     }
     if (l < kLMin) l = kLMin;
     if (l > 1.0) l = 1.0;
@@ -434,7 +469,6 @@ int zolo_pd(zolo_handle h, int m, int n, const double* A, int lda, double alpha,
     inf.r_used = r;
     inf.t_stage[0] += lap();
 
-    StepCtx cx{h, &w, m, n};
     bool g_valid = false;   // G holds X^T X of the current X
     int status = ZOLO_NOT_CONVERGED;
     Coeffs co;
@@ -498,7 +532,18 @@ int zolo_pd(zolo_handle h, int m, int n, const double* A, int lda, double alpha,
                     break;
                 }
                 const double bnd = std::sqrt((double)n) * d;
-                l = bnd < 1.0 ? std::sqrt(std::max(kLMin * kLMin, 1.0 - bnd)) : l_pred / 10.0;
+                if (bnd < 1.0) {
+                    l = std::sqrt(std::max(kLMin * kLMin, 1.0 - bnd));
+                } else {
+                    // The bound from d is void: l was above sigma_min and
+                    // some singular values are still far from 1.  Restart
+                    // from the condition estimate of the current X.
+                    if ((rc = condition_estimate(cx, w.X, &l))) return finish(rc);
+                    l = std::min(1.0, std::max(kLMin, l));
+                    g_valid = false;
+                    ++inf.l_reestimates;
+                    inf.t_stage[0] += lap();
+                }
             } else {
                 l = l_pred;
             }

@@ -89,3 +89,37 @@ def batch_specs(count=512, seed=4000, nmin=64, nmax=1024, kmin=2.0, kmax=12.0):
         out.append({"m": m, "n": n, "kappa": kappa, "seed_u": seed + 10 * i + 1,
                     "seed_v": seed + 10 * i + 2})
     return out
+
+
+def training_spectra(count, seed, nmin=128, nmax=2048, kmin=1.0, kmax=16.0):
+    """Spectra for training the learned l/r estimator: n ~ U{nmin..nmax},
+    m ~ U{n..2n}, log10 kappa ~ U[kmin, kmax]; half log-spaced from 1 to
+    1/kappa, half clustered: 2-4 clusters at log-uniform positions in
+    [1/kappa, 1] that always include 1 and 1/kappa, each value jittered by a
+    factor in [0.95, 1.05] (then 1 and 1/kappa restored as the extremes).
+    Returns (ms, ns, kappas, sigmas, families) with sigmas a list of
+    descending arrays and families 0 (log-spaced) or 1 (clustered)."""
+    rng = np.random.default_rng(seed)
+    ms, ns, ks, sig, fam = [], [], [], [], []
+    for _ in range(count):
+        n = int(rng.integers(nmin, nmax + 1))
+        m = int(rng.integers(n, 2 * n + 1))
+        kappa = float(10.0 ** rng.uniform(kmin, kmax))
+        clustered = rng.random() >= 0.5
+        if not clustered:
+            s = logspaced_sigma(n, kappa)
+        else:
+            nc = int(rng.integers(2, 5))
+            centres = np.concatenate([[0.0, -np.log10(kappa)],
+                                      -np.log10(kappa) * rng.random(nc - 2)])
+            which = rng.integers(0, nc, size=n)
+            which[0], which[-1] = 0, 1
+            s = 10.0 ** centres[which] * rng.uniform(0.95, 1.05, size=n)
+            s = np.sort(np.clip(s, 1.0 / kappa, 1.0))[::-1]
+            s[0], s[-1] = 1.0, 1.0 / kappa
+        ms.append(m)
+        ns.append(n)
+        ks.append(kappa)
+        sig.append(np.asarray(s, dtype=np.float64))
+        fam.append(int(clustered))
+    return ms, ns, ks, sig, fam

@@ -25,12 +25,13 @@ STATUS = {0: "ok", 1: "not converged", 2: "non-finite input", 3: "allocation fai
 
 class ZoloOpts(ctypes.Structure):
     _fields_ = [("max_iter", c_int), ("stop_rule", c_int), ("tau", c_double), ("chol_switch", c_double),
-                ("qr_variant", c_int), ("precision", c_int), ("compute_errors", c_int),
-                ("reserved", c_int * 9)]
+                ("qr_variant", c_int), ("precision", c_int), ("compute_errors", c_int), ("l_source", c_int),
+                ("reserved", c_int * 8)]
 
 
 class ZoloInfo(ctypes.Structure):
-    _fields_ = [("status", c_int), ("iters", c_int), ("r_used", c_int), ("chol_fallbacks", c_int),
+    _fields_ = [("status", c_int), ("iters", c_int), ("r_used", c_int), ("chol_fallbacks", c_int), ("l_from", c_int),
+                ("l_reestimates", c_int),
                 ("kind", ctypes.c_char * (MAX_ITER + 1)), ("prec", ctypes.c_char * (MAX_ITER + 1)),
                 ("alpha", c_double), ("l0", c_double),
                 ("l_seq", c_double * MAX_ITER), ("orth_check", c_double), ("t_stage", c_double * 8),
@@ -40,6 +41,8 @@ class ZoloInfo(ctypes.Structure):
     def as_dict(self):
         it = self.iters
         return {"status": self.status, "iters": it, "r": self.r_used, "chol_fallbacks": self.chol_fallbacks,
+                "l_from": ("given", "condition estimate", "learned")[self.l_from],
+                "l_reestimates": self.l_reestimates,
                 "kinds": list(self.kind.decode()), "prec": self.prec.decode(), "alpha": self.alpha,
                 "l0": self.l0,
                 "ls": list(self.l_seq[:it]), "orth_check": self.orth_check,
@@ -52,7 +55,11 @@ _lib = None
 EXPORTS = ["zolo_default_opts", "zolo_create", "zolo_set_stream", "zolo_destroy", "zolo_coeffs", "zolo_pd",
            "zolo_pd_batched", "zolo_svd", "zolo_dgemm", "zolo_dpotrf_batched", "zolo_dtrtri_batched",
            "zolo_sgemm", "zolo_spotrf_batched", "zolo_strtri_batched", "zolo_structured_qr_batched",
-           "zolo_stats_enable", "zolo_stats_reset", "zolo_stats_get", "zolo_stats_count"]
+           "zolo_stats_enable", "zolo_stats_reset", "zolo_stats_get", "zolo_stats_count",
+           "zolo_sketch_features", "zolo_surrogate_features", "zolo_mlp_stats", "zolo_mlp_work_elems",
+           "zolo_mlp_forward", "zolo_mlp_loss", "zolo_mlp_backward", "zolo_mlp_adam", "zolo_mlp_train",
+           "zolo_set_estimator", "zolo_choose_r"]
+NF, MLP_NPARAMS, MLP_NSTATS = 39, 6928, 78
 
 
 def load():
@@ -94,9 +101,23 @@ def load():
     lib.zolo_stats_reset.argtypes = []
     lib.zolo_stats_count.argtypes = []
     lib.zolo_stats_get.argtypes = [c_int, ctypes.c_char_p, c_int, ctypes.POINTER(c_longlong), D, D]
+    F = ctypes.c_float
+    U64 = ctypes.c_ulonglong
+    lib.zolo_sketch_features.argtypes = [P, c_int, c_int, P, c_int, U64, D]
+    lib.zolo_surrogate_features.argtypes = [P, c_int, IP, IP, P, c_int, U64, U64, P]
+    lib.zolo_mlp_stats.argtypes = [P, c_int, P, P]
+    lib.zolo_mlp_work_elems.argtypes = [c_int]
+    lib.zolo_mlp_forward.argtypes = [P, c_int, P, P, P, P]
+    lib.zolo_mlp_loss.argtypes = [P, c_int, P, P, F, F, P, ctypes.POINTER(F)]
+    lib.zolo_mlp_backward.argtypes = [P, c_int, P, P, P, P]
+    lib.zolo_mlp_adam.argtypes = [P, P, P, P, P, c_int, F, F, F, F]
+    lib.zolo_mlp_train.argtypes = [P, c_int, c_int, c_int, P, P, P, P, P, P, c_int, F, F, F, P, P, P]
+    lib.zolo_set_estimator.argtypes = [P, P, c_int]
+    lib.zolo_choose_r.argtypes = [c_double]
     for name in EXPORTS:
         if name not in ("zolo_default_opts",):
             getattr(lib, name).restype = c_int
+    lib.zolo_mlp_work_elems.restype = c_longlong
     _lib = lib
     return lib
 
@@ -194,12 +215,17 @@ class Zolo:
     def options(**kw):
         o = ZoloOpts()
         load().zolo_default_opts(ctypes.byref(o))
-        names = {"max_iter", "stop_rule", "tau", "chol_switch", "qr_variant", "precision", "compute_errors"}
+        names = {"max_iter", "stop_rule", "tau", "chol_switch", "qr_variant", "precision", "compute_errors",
+                 "l_source"}
         for k, v in kw.items():
             if k not in names:
                 raise TypeError(f"unknown option {k}")
             if k == "stop_rule" and isinstance(v, str):
                 v = {"verified": 0, "paper": 1}[v]
+            if k == "l_source" and isinstance(v, str):
+                v = {"condest": 0, "learned": 1}[v]
+            if k == "precision" and isinstance(v, str):
+                v = {"fp64": 0, "mixed": 1}[v]
             setattr(o, k, v)
         return o
 
@@ -330,6 +356,114 @@ class Zolo:
             _raise(rc, f"zolo_{p}trtri_batched")
         return Ib.transpose(-1, -2)
 
+    # -- learned l/r estimator (zolo_learn.h) -------------------------------
+    def sketch_features(self, X0, seed):
+        """Features (numpy, 39) of X0 (float64 device tensor, m x n)."""
+        import numpy as np
+        _check_tensor(X0, "X0")
+        Xc, ld = _colmajor(X0)
+        m, n = X0.shape
+        out = np.zeros(NF)
+        rc = self.lib.zolo_sketch_features(self.h, m, n, c_void_p(Xc.data_ptr()), ld, int(seed),
+                                           out.ctypes.data_as(ctypes.POINTER(c_double)))
+        if rc:
+            _raise(rc, "zolo_sketch_features")
+        return out
+
+    def surrogate_features(self, sigma, ms, ns, seed, first_index=0):
+        """Surrogate features (G4) of `count` spectra.  sigma: contiguous
+        float64 device tensor (count, ldsigma), row b holding the ns[b] values
+        of spectrum b; ms: row counts.  Returns a (count, 39) float64 device
+        tensor (each feature vector contiguous)."""
+        torch = _torch()
+        count, ldsig = sigma.shape
+        if not sigma.is_contiguous() or sigma.dtype != torch.float64:
+            raise TypeError("sigma must be a contiguous float64 device tensor (count, ldsigma)")
+        feat = torch.empty((count, NF), dtype=torch.float64, device=sigma.device)
+        mv = (c_int * count)(*[int(x) for x in ms])
+        nv = (c_int * count)(*[int(x) for x in ns])
+        rc = self.lib.zolo_surrogate_features(self.h, count, mv, nv, c_void_p(sigma.data_ptr()), ldsig, int(seed),
+                                              int(first_index), c_void_p(feat.data_ptr()))
+        if rc:
+            _raise(rc, "zolo_surrogate_features")
+        return feat
+
+    def mlp_stats(self, feat, params):
+        rc = self.lib.zolo_mlp_stats(self.h, feat.shape[0], c_void_p(feat.data_ptr()), c_void_p(params.data_ptr()))
+        if rc:
+            _raise(rc, "zolo_mlp_stats")
+
+    def mlp_work(self, batch):
+        torch = _torch()
+        return torch.zeros(int(self.lib.zolo_mlp_work_elems(batch)) + 4 * batch, dtype=torch.float32,
+                           device="cuda")
+
+    def mlp_forward(self, params, feat, work=None):
+        """y (batch, 2) float32 for feature rows feat (batch, 39) float64."""
+        torch = _torch()
+        batch = feat.shape[0]
+        work = self.mlp_work(batch) if work is None else work
+        y = torch.empty((batch, 2), dtype=torch.float32, device=feat.device)
+        rc = self.lib.zolo_mlp_forward(self.h, batch, c_void_p(params.data_ptr()), c_void_p(feat.data_ptr()),
+                                       c_void_p(y.data_ptr()), c_void_p(work.data_ptr()))
+        if rc:
+            _raise(rc, "zolo_mlp_forward")
+        return y, work
+
+    def mlp_loss(self, y, t, q=0.1, c_r=0.1):
+        torch = _torch()
+        dy = torch.empty_like(y)
+        loss = ctypes.c_float()
+        rc = self.lib.zolo_mlp_loss(self.h, y.shape[0], c_void_p(y.data_ptr()), c_void_p(t.data_ptr()),
+                                    float(q), float(c_r), c_void_p(dy.data_ptr()), ctypes.byref(loss))
+        if rc:
+            _raise(rc, "zolo_mlp_loss")
+        return loss.value, dy
+
+    def mlp_backward(self, params, work, dy):
+        torch = _torch()
+        grad = torch.empty(MLP_NPARAMS, dtype=torch.float32, device=dy.device)
+        rc = self.lib.zolo_mlp_backward(self.h, dy.shape[0], c_void_p(params.data_ptr()), c_void_p(work.data_ptr()),
+                                        c_void_p(dy.data_ptr()), c_void_p(grad.data_ptr()))
+        if rc:
+            _raise(rc, "zolo_mlp_backward")
+        return grad
+
+    def mlp_adam(self, params, grad, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+        rc = self.lib.zolo_mlp_adam(self.h, c_void_p(params.data_ptr()), c_void_p(grad.data_ptr()),
+                                    c_void_p(m.data_ptr()), c_void_p(v.data_ptr()), int(t), float(lr), float(b1),
+                                    float(b2), float(eps))
+        if rc:
+            _raise(rc, "zolo_mlp_adam")
+
+    def mlp_train(self, feat, t, idx, params, m, v, t0, lr, q=0.1, c_r=0.1, work=None, grad=None):
+        """len(idx) // batch steps; idx is an int32 device tensor (steps, batch).
+        Returns the per-step losses (float32 device tensor)."""
+        torch = _torch()
+        steps, batch = idx.shape
+        work = self.mlp_work(batch) if work is None else work
+        grad = torch.empty(MLP_NPARAMS, dtype=torch.float32, device=feat.device) if grad is None else grad
+        losses = torch.empty(steps, dtype=torch.float32, device=feat.device)
+        rc = self.lib.zolo_mlp_train(self.h, steps, batch, feat.shape[0], c_void_p(feat.data_ptr()),
+                                     c_void_p(t.data_ptr()), c_void_p(idx.data_ptr()), c_void_p(params.data_ptr()),
+                                     c_void_p(m.data_ptr()), c_void_p(v.data_ptr()), int(t0), float(lr), float(q),
+                                     float(c_r), c_void_p(work.data_ptr()), c_void_p(grad.data_ptr()),
+                                     c_void_p(losses.data_ptr()))
+        if rc:
+            _raise(rc, "zolo_mlp_train")
+        return losses
+
+    def set_estimator(self, params):
+        """Install trained parameters (numpy float32, 6928) or remove (None)."""
+        import numpy as np
+        if params is None:
+            rc = self.lib.zolo_set_estimator(self.h, None, 0)
+        else:
+            p = np.ascontiguousarray(params, dtype=np.float32)
+            rc = self.lib.zolo_set_estimator(self.h, c_void_p(p.ctypes.data), p.size)
+        if rc:
+            _raise(rc, "zolo_set_estimator")
+
     def structured_qr(self, Y, pivots=None, form_q=True):
         """QR of [Y_b; p_b I] (pivots given) or of Y_b (pivots None) for a
         (batch, m, n) stack.  Returns (Q or Householder vectors, R): Q is
@@ -346,3 +480,8 @@ class Zolo:
         if rc:
             _raise(rc, "zolo_structured_qr_batched")
         return Mb.transpose(-1, -2), Rb.transpose(-1, -2)
+
+
+def choose_r(l):
+    """The library's degree policy (host only)."""
+    return int(load().zolo_choose_r(float(l)))

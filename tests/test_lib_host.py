@@ -15,9 +15,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def declared_functions():
     names = []
-    for h in ("zolo.h", "zolo_blocks.h", "zolo_stats.h"):
+    for h in ("zolo.h", "zolo_blocks.h", "zolo_stats.h", "zolo_learn.h"):
         txt = open(os.path.join(ROOT, "include", h)).read()
-        names += re.findall(r"^\s*(?:int|void)\s+(zolo_\w+)\s*\(", txt, flags=re.M)
+        names += re.findall(r"^\s*(?:int|void|long long)\s+(zolo_\w+)\s*\(", txt, flags=re.M)
     return names
 
 
@@ -77,3 +77,16 @@ def test_table1_through_library(lib):
                 k += 1
             got.append(k)
         assert got == row, rs
+
+
+def test_choose_r_matches_oracle_policy(lib):
+    from paper_1806_06204_amd import zolo
+    for l in [1e-20, 1e-16, 1e-12, 1e-8, 1e-4, 0.01, 0.3, 0.9, 1.0]:
+        assert zolo.choose_r(l) == oc.choose_r(l), l
+
+
+def test_learned_layout_constants(lib):
+    from oracle import learned as OL
+    from paper_1806_06204_amd import zolo
+    assert (zolo.NF, zolo.MLP_NPARAMS, zolo.MLP_NSTATS) == (OL.NF, OL.N_PARAMS, OL.N_STATS)
+    assert lib.zolo_mlp_work_elems(100) >= (OL.NF + 4 * OL.NH) * 100

@@ -169,3 +169,17 @@ def test_svd():
     assert np.allclose(S, s, rtol=1e-10, atol=1e-14)   # eigenvalues: absolute error ~ eps ||H||
     assert Z.svd_residual_paper(A, Uc, S, Vc) <= 1e-13
     assert Z.orth_paper(Uc) <= 1e-15 and Z.orth_paper(Vc) <= 1e-15
+
+
+@pytest.mark.parametrize("m,n,kappa,l_given,r", [(120, 80, 1e12, 1e-4, 4), (90, 90, 1e14, 1e-2, 3),
+                                                  (150, 100, 1e8, 0.5, 2)])
+def test_overestimated_l_is_reestimated(m, n, kappa, l_given, r):
+    # R8: an l above sigma_min leaves singular values far below 1 after the
+    # predicted last step; sqrt(n) d >= 1 then voids the bound from d and the
+    # condition estimate of the current X restarts the recursion.  The result
+    # is still the exact polar decomposition of the worked case.
+    A, U, s, V = W.svd_matrix(m, n, kappa, 5, 6)
+    Qp, H, info = Z.zolo_pd(A, 1.0, l_given, r)
+    assert info["status"] == 0 and info["l_reestimates"] >= 1 and info["iters"] <= 7
+    assert Z.backward_error(A, Qp, H) <= 1e-13 and Z.orthogonality(Qp) <= 1e-13
+    assert np.linalg.norm(H - (V * s) @ V.T) <= 1e-13 * np.linalg.norm(s)
