@@ -148,6 +148,91 @@ def bench_precision_study(args):
     z.close()
 
 
+def bench_learned(args):
+    """Learned l/r estimator: train on generated spectra with the library's
+    GPU kernels, evaluate on held-out spectra, then compare the learned and
+    the condition-estimate paths inside Zolo-PD and Zolo-SVD on n x n inputs
+    (the log-spaced generator and the sparse-pattern matrix)."""
+    import numpy as np
+    import torch
+    from paper_1806_06204_amd import learned as L
+    from paper_1806_06204_amd import workloads as W
+    from paper_1806_06204_amd import zolo
+    z = zolo.Zolo()
+    log = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    # n up to 8192: the network does not extrapolate in n (trained on n <= 2048
+    # it misses l by ~4 decades at n = 4096-8192), so the training range
+    # covers the sizes it is evaluated at.
+    feats, T, _ = L.build_set(z, args.train_count, seed=11, feature_seed=12, nmin=128, nmax=8192)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    log(f"training set: {args.train_count} spectra in {t_build:.1f} s")
+    t0 = time.perf_counter()
+    params, hist = L.train(z, feats, T, epochs=60, batch=512, lr=3e-3, seed=13, q=0.05)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"trained in {t_train:.1f} s, loss {hist[0]:.3f} -> {hist[-1]:.3f}")
+    held = {}
+    for lo, hi in ((128, 2048), (2048, 8192)):
+        fe, Te, specs = L.build_set(z, 4096, seed=21, feature_seed=22, nmin=lo, nmax=hi)
+        fam = np.array(specs[3])
+        held[f"n{lo}-{hi}"] = {"log_spaced": L.evaluate(z, params, fe, Te, fam == 0),
+                               "clustered": L.evaluate(z, params, fe, Te, fam == 1)}
+        del fe, Te
+    del feats, T
+    z.set_estimator(params.cpu().numpy())
+    n = args.n
+    cases = []
+    for kappa in (1e8, 1e16):
+        A = W.svd_matrix(n, n, kappa, 1000 + 3, 2000 + 3)[0]
+        cases.append((f"log-spaced kappa={kappa:g}", torch.from_numpy(np.ascontiguousarray(A.T)).to("cuda:0").t(),
+                      1.0))
+    Sp = W.sparse_pattern(n)
+    cases.append(("sparse pattern (band 64, 1% off-band)",
+                  torch.from_numpy(np.ascontiguousarray(Sp.T)).to("cuda:0").t(), None))
+    rows = []
+    for name, A, alpha in cases:
+        row = {"matrix": name}
+        for path, src in (("condest", 0), ("learned", 1)):
+            z.pd(A, alpha=alpha, l_source=src)                       # warm-up
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, _, inf = z.pd(A, alpha=alpha, l_source=src)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            _, _, e = z.pd(A, alpha=alpha, l_source=src, compute_errors=1)
+            row[path] = {"pd_ms": dt * 1e3, "estimate_ms": inf["t_stage_ms"][0], "l0": inf["l0"], "r": inf["r"],
+                         "schedule": "".join(inf["kinds"]), "l_from": inf["l_from"],
+                         "l_reestimates": inf["l_reestimates"], "bwd_err": e["bwd_err"], "orth_err": e["orth_err"]}
+            log(f"{name} {path}: {row[path]}")
+        row["pd_speedup"] = row["condest"]["pd_ms"] / row["learned"]["pd_ms"]
+        rows.append(row)
+    # Full Zolo-SVD on the kappa = 1e16 matrix with each path.
+    svd = {}
+    name, A, alpha = cases[1]
+    for path, src in (("condest", 0), ("learned", 1)):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        U, S, V, inf = z.svd(A, alpha=alpha, l_source=src)
+        torch.cuda.synchronize()
+        svd[path] = {"total_ms": (time.perf_counter() - t1) * 1e3, "pd_ms": sum(inf["t_stage_ms"][:5]),
+                     "eig_ms": inf["t_stage_ms"][5], "u_ms": inf["t_stage_ms"][6], "schedule": "".join(inf["kinds"]),
+                     "r": inf["r"], "l0": inf["l0"]}
+        log(f"svd {path}: {svd[path]}")
+        del U, V
+    z.set_estimator(None)
+    out = {"metric": "learned vs condition-estimate l, Zolo-PD / Zolo-SVD", "n_gpus": 1, "dtype": "f64 (network f32)",
+           "data": "synthetic",
+           "config": {"workload": f"train on {args.train_count} generated spectra (n 128-8192, kappa 1e1-1e16, half "
+                                  f"log-spaced, half clustered); evaluate on {n}x{n} inputs", "n": n},
+           "training": {"spectra": args.train_count, "build_s": t_build, "train_s": t_train, "epochs": 60,
+                        "loss_first": hist[0], "loss_last": hist[-1]},
+           "held_out": held, "pd": rows, "svd_kappa_1e16": svd}
+    print(json.dumps(out), flush=True)
+    z.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +243,10 @@ def main():
     ap.add_argument("--r", type=int, default=8)
     ap.add_argument("--cpu-sample", type=int, default=640)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--learned", action="store_true",
+                    help="instead: train the learned l/r estimator and compare it with the condition estimate "
+                         "(use with --n 4096)")
+    ap.add_argument("--train-count", type=int, default=100000)
     ap.add_argument("--precision-study", action="store_true",
                     help="instead: FP64 vs mixed at kappa 1e4/1e8/1e12 (use with --r 3)")
     ap.add_argument("--batched", type=int, default=0,
@@ -178,6 +267,8 @@ def main():
         return bench_batched(args)
     if args.precision_study:
         return bench_precision_study(args)
+    if args.learned:
+        return bench_learned(args)
     n, kappa, r = args.n, args.kappa, args.r
     print(f"[bench] generating {n}x{n} kappa={kappa:g} input", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
