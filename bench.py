@@ -32,6 +32,38 @@ FP64_PEAK_TFLOPS = 78.6     # MI355X dense FP64 matrix peak
 METRIC = "Zolo-PD time & TFLOP/s, n=8192 kappa=1e16, mixed vs FP64 at bwd err <=1e-13"
 
 
+def kernel_source_hash():
+    """sha256 of the GEMM kernel's sources; a counter summary applies only to
+    the source it was measured on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("gemm.hip", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_1806_06204_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel_stat_name):
+    """HBM bytes per launch of the dominant kernel from the rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary in profiles/, if one was taken on the
+    current GEMM source for this kernel; else None."""
+    d = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(d):
+        return None
+    digest = kernel_source_hash()
+    for f in sorted(os.listdir(d)):
+        if not f.endswith("_traffic.txt"):
+            continue
+        kv = {}
+        for line in open(os.path.join(d, f)):
+            if ":" in line and not line.startswith(" "):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        if kv.get("stat_name") == kernel_stat_name and kv.get("source_sha256") == digest:
+            return {"bytes_per_launch": float(kv["traffic_bytes_per_launch"]), "file": "profiles/" + f}
+    return None
+
+
 def paper_flops(m, n, r, kinds, checks):
     f = 0.0
     for k in kinds:
@@ -243,6 +275,9 @@ def main():
     ap.add_argument("--r", type=int, default=8)
     ap.add_argument("--cpu-sample", type=int, default=640)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="first copy this many MiB device to device (a dispatch of known traffic for "
+                         "calibrating rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     ap.add_argument("--learned", action="store_true",
                     help="instead: train the learned l/r estimator and compare it with the condition estimate "
                          "(use with --n 4096)")
@@ -277,6 +312,14 @@ def main():
     A = torch.from_numpy(np.ascontiguousarray(A_np.T)).to("cuda:0").t()   # column-major view
     z = zolo.Zolo()
     l = 1.0 / kappa
+    if args.calibrate_copy_mib > 0:
+        src = torch.ones(args.calibrate_copy_mib * 2 ** 17, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy of {args.calibrate_copy_mib} MiB done", file=sys.stderr, flush=True)
+        del src, dst
     for i in range(args.warmup):
         _, _, info = z.pd(A, alpha=1.0, l=l, r=r)
         print(f"[bench] warmup {i}: {''.join(info['kinds'])} {info['t_stage_ms'][7]:.1f} ms",
@@ -301,8 +344,9 @@ def main():
           file=sys.stderr, flush=True)
 
     # Dominant kernel by GPU time.
-    name, (launches, ms, flops) = max(st.items(), key=lambda kv: kv[1][1])
+    name, (launches, ms, flops, nbytes) = max(st.items(), key=lambda kv: kv[1][1])
     achieved = (flops / launches) / (ms / launches * 1e-3) / 1e12
+    traffic = measured_traffic(name)
     gpu_ms_total = sum(v[1] for v in st.values()) / args.steps
 
     # Accuracy of the same solve (separate call, errors computed on the GPU),
@@ -353,12 +397,17 @@ def main():
                      "H": info["t_stage_ms"][4]},
         "gpu_kernel_ms_per_step": gpu_ms_total,
         "kernels": {k: {"launches_per_step": v[0] / args.steps, "ms_per_step": v[1] / args.steps,
-                        "tflops": (v[2] / (v[1] * 1e-3) / 1e12) if v[1] > 0 else None}
+                        "tflops": (v[2] / (v[1] * 1e-3) / 1e12) if v[1] > 0 else None,
+                        "algorithmic_GB_s": (v[3] / (v[1] * 1e-3) / 1e9) if v[1] > 0 and v[3] > 0 else None}
                     for k, v in sorted(st.items(), key=lambda kv: -kv[1][1])},
         "accuracy": {"bwd_err": vinfo["bwd_err"], "orth_err": vinfo["orth_err"],
                      "h_sampled_err": h_err, "status": vinfo["status"]},
         "roofline": {"bound": "mfma", "kernel": name, "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": traffic["bytes_per_launch"] if traffic else None,
+                     "traffic_source": traffic["file"] if traffic else "no counter summary for the current source",
+                     "algorithmic_bytes_per_launch": nbytes / launches,
+                     "algorithmic_GB_s": (nbytes / launches) / (ms / launches * 1e-3) / 1e9,
                      "launches_per_step": launches / args.steps,
                      "mean_launch_ms": ms / launches},
         "mixed": mixed,

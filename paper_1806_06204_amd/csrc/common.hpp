@@ -76,6 +76,20 @@ double gemm_flops(const GemmDescT<T>& d) {
     return f;
 }
 
+// Algorithmic memory traffic of a descriptor in bytes: the used parts of A and
+// B once per batch, Cin when beta != 0 and C once per output (triangular
+// operands and upper-tile outputs halved).
+template <class T>
+double gemm_bytes(const GemmDescT<T>& d) {
+    const double nb = (double)d.batch * d.batch2, nout = (double)(d.reduce ? 1 : d.batch) * d.batch2;
+    double a = (double)d.m * d.k, b = (double)d.k * d.n, c = (double)d.m * d.n;
+    if (d.flags & (kAUpper | kALower)) a *= 0.5;
+    if (d.flags & (kBUpper | kBLower)) b *= 0.5;
+    if (d.flags & kCUpperTiles) c *= 0.5;
+    const double cin = (d.Cin && d.beta != 0.0) ? c : 0.0;
+    return sizeof(T) * (nb * (a + b) + nout * (c + cin));
+}
+
 // ---------------------------------------------------------------------------
 // Small device helpers
 // ---------------------------------------------------------------------------

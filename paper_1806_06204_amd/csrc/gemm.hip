@@ -198,7 +198,7 @@ hipError_t launch_bm_bn(const GemmDescT<T>& d, hipStream_t s) {
     } else {
         name[0] = 0;
     }
-    StatScope sc(name, s, gemm_flops(d));
+    StatScope sc(name, s, gemm_flops(d), gemm_bytes(d));
     if (which == 0) gemm_kernel<T, BM, BN, false, false><<<grid, 256, 0, s>>>(d);
     else if (which == 1) gemm_kernel<T, BM, BN, false, true><<<grid, 256, 0, s>>>(d);
     else if (which == 2) gemm_kernel<T, BM, BN, true, false><<<grid, 256, 0, s>>>(d);

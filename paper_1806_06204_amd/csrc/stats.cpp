@@ -15,6 +15,7 @@ struct Entry {
     long long launches = 0;
     double ms = 0.0;
     double flops = 0.0;
+    double bytes = 0.0;
 };
 
 struct Pending {
@@ -73,12 +74,13 @@ Registry& reg() {
 
 bool stats_on() { return reg().on; }
 
-StatScope::StatScope(const char* name, hipStream_t st, double flops) {
+StatScope::StatScope(const char* name, hipStream_t st, double flops, double bytes) {
     Registry& r = reg();
     if (!r.on) return;
     slot_ = r.slot_for(name);
     r.entries[slot_].launches += 1;
     r.entries[slot_].flops += flops;
+    r.entries[slot_].bytes += bytes;
     pair_ = r.take_pair();
     st_ = st;
     if (pair_ >= 0 && hipEventRecord(r.ev0[pair_], st) != hipSuccess) pair_ = -1;
@@ -109,7 +111,8 @@ int zolo_stats_reset(void) {
 
 int zolo_stats_count(void) { return (int)zolo::reg().entries.size(); }
 
-int zolo_stats_get(int index, char* name, int name_len, long long* launches, double* ms, double* flops) {
+int zolo_stats_get(int index, char* name, int name_len, long long* launches, double* ms, double* flops,
+                   double* bytes) {
     zolo::Registry& r = zolo::reg();
     r.collect();
     if (index < 0 || index >= (int)r.entries.size()) return -1;
@@ -121,6 +124,7 @@ int zolo_stats_get(int index, char* name, int name_len, long long* launches, dou
     if (launches) *launches = e.launches;
     if (ms) *ms = e.ms;
     if (flops) *flops = e.flops;
+    if (bytes) *bytes = e.bytes;
     return 0;
 }
 

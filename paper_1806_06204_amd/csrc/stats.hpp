@@ -9,7 +9,7 @@ bool stats_on();
 // Brackets one launch: construct before, call end() after the launch.
 class StatScope {
   public:
-    StatScope(const char* name, hipStream_t st, double flops);
+    StatScope(const char* name, hipStream_t st, double flops, double bytes = 0.0);
     void end();
 
   private:

@@ -100,7 +100,7 @@ def load():
     lib.zolo_stats_enable.argtypes = [c_int]
     lib.zolo_stats_reset.argtypes = []
     lib.zolo_stats_count.argtypes = []
-    lib.zolo_stats_get.argtypes = [c_int, ctypes.c_char_p, c_int, ctypes.POINTER(c_longlong), D, D]
+    lib.zolo_stats_get.argtypes = [c_int, ctypes.c_char_p, c_int, ctypes.POINTER(c_longlong), D, D, D]
     F = ctypes.c_float
     U64 = ctypes.c_ulonglong
     lib.zolo_sketch_features.argtypes = [P, c_int, c_int, P, c_int, U64, D]
@@ -144,7 +144,7 @@ def stats_reset():
 
 
 def stats():
-    """Per-kernel launch statistics: {name: (launches, ms, flops)}."""
+    """Per-kernel launch statistics: {name: (launches, ms, flops, bytes)}."""
     lib = load()
     out = {}
     for i in range(lib.zolo_stats_count()):
@@ -152,8 +152,10 @@ def stats():
         n = c_longlong()
         ms = c_double()
         fl = c_double()
-        if lib.zolo_stats_get(i, name, 128, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl)) == 0:
-            out[name.value.decode()] = (n.value, ms.value, fl.value)
+        by = c_double()
+        if lib.zolo_stats_get(i, name, 128, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl),
+                              ctypes.byref(by)) == 0:
+            out[name.value.decode()] = (n.value, ms.value, fl.value, by.value)
     return out
 
 
