@@ -130,6 +130,30 @@ __global__ __launch_bounds__(256, (BM * BN >= 128 * 128) ? 1 : 2) void gemm_kern
         }
     };
 
+    // The Cin tile is loaded before the k-loop so that its latency hides
+    // behind the MFMAs (read in the epilogue, one load would wait for the
+    // previous store: Cin and C may be the same array).  Out-of-range lanes
+    // load a valid address and drop the value.
+    const int ob = d.reduce ? 0 : blockIdx.y;
+    T* __restrict__ C = d.C + (long long)ob * d.strideC + (long long)blockIdx.z * d.strideC2;
+    const T* Cin = d.Cin ? d.Cin + (long long)ob * d.strideCin + (long long)blockIdx.z * d.strideCin2 : nullptr;
+    const T alpha = (T)d.alpha, beta = (T)d.beta;
+    const bool use_cin = Cin != nullptr && d.beta != 0.0;
+    T cin[FM][FN][4];
+    if (use_cin) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int gi = row0 + wm + i * 16 + Mfma<T>::row(lane, e);
+                    const int gj = col0 + wn + j * 16 + (lane & 15);
+                    const bool ok = gi < d.m && gj < d.n;
+                    cin[i][j][e] = Cin[ok ? gi + (long long)gj * d.ldcin : 0];
+                }
+    }
+
     if (ntiles > 0) {
         gload(0);
         lstore(0);
@@ -162,11 +186,6 @@ __global__ __launch_bounds__(256, (BM * BN >= 128 * 128) ? 1 : 2) void gemm_kern
         }
     }
 
-    const int ob = d.reduce ? 0 : blockIdx.y;
-    T* __restrict__ C = d.C + (long long)ob * d.strideC + (long long)blockIdx.z * d.strideC2;
-    const T* Cin = d.Cin ? d.Cin + (long long)ob * d.strideCin + (long long)blockIdx.z * d.strideCin2 : nullptr;
-    const T alpha = (T)d.alpha, beta = (T)d.beta;
-    const bool use_cin = Cin != nullptr && d.beta != 0.0;
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -180,7 +199,7 @@ __global__ __launch_bounds__(256, (BM * BN >= 128 * 128) ? 1 : 2) void gemm_kern
                 if (fl & kCStoreLower) ok = ok && gi >= gj;
                 if (ok) {
                     T v = alpha * acc[i][j][e];
-                    if (use_cin) v += beta * Cin[gi + (long long)gj * d.ldcin];
+                    if (use_cin) v += beta * cin[i][j][e];
                     C[gi + (long long)gj * d.ldc] = v;
                 }
             }
@@ -217,7 +236,11 @@ hipError_t gemm_dispatch(const GemmDescT<T>& d, hipStream_t s) {
         (long long)((d.m + 127) / 128) * ((d.n + 127) / 128) * (d.reduce ? 1 : d.batch) * d.batch2;
     const bool small_m = d.m <= 64 || big_tiles < 256;
     const bool small_n = d.n <= 64 || big_tiles < 256;
-    if (small_m && small_n) return launch_bm_bn<T, 64, 64>(d, s);
+    // Short-K products (the rank-64 trailing updates) are bound by moving C,
+    // not by the MFMAs: 64 x 64 tiles run two workgroups per CU, so one
+    // tile's loads and stores overlap another's MFMAs (measured 2.0-2.2 TB/s
+    // with 128 x 128 tiles, 2.5-2.7 TB/s with 64 x 64 on 8256 x n x 64 x 8).
+    if (d.k <= 128 || (small_m && small_n)) return launch_bm_bn<T, 64, 64>(d, s);
     if (small_m) return launch_bm_bn<T, 64, 128>(d, s);
     if (small_n) return launch_bm_bn<T, 128, 64>(d, s);
     return launch_bm_bn<T, 128, 128>(d, s);
