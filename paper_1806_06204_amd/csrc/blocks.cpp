@@ -156,12 +156,17 @@ int zolo_structured_qr_batched(zolo_handle h, int m, int n, const double* pivots
     const size_t blk = (size_t)batch * npanels * kPanelNB * kPanelNB;
     const size_t part = qr_partials_elems(m, e, batch, h->panel_coresident);
     size_t off = 0;
-    const size_t need = 8 * 256 + sizeof(double) * ((size_t)batch * kPanelNB * n + 2 * blk +
-                                                    (size_t)batch * kPanelNB * kPanelNB + part) +
+    const size_t need = 12 * 256 + sizeof(double) * (2 * qr_w_elems(n, batch) + qr_tb_elems(n, batch) + 2 * blk +
+                                                     kQrSplitElems +
+                                                     (size_t)batch * kPanelNB * kPanelNB + part) +
                         sizeof(unsigned) * (size_t)batch * npanels + 64;
     if (int rc = grow(h, need)) return rc;
     QrWork w;
-    w.W = (double*)bump(h->arena, off, sizeof(double) * (size_t)batch * kPanelNB * n);
+    w.W = (double*)bump(h->arena, off, sizeof(double) * qr_w_elems(n, batch));
+    w.W2 = (double*)bump(h->arena, off, sizeof(double) * qr_w_elems(n, batch));
+    w.Tb = (double*)bump(h->arena, off, sizeof(double) * qr_tb_elems(n, batch));
+    w.splitk = (double*)bump(h->arena, off, sizeof(double) * kQrSplitElems);
+    w.splitk_elems = kQrSplitElems;
     w.T = (double*)bump(h->arena, off, sizeof(double) * blk);
     w.Rd = (double*)bump(h->arena, off, sizeof(double) * blk);
     w.S = (double*)bump(h->arena, off, sizeof(double) * (size_t)batch * kPanelNB * kPanelNB);

@@ -54,6 +54,11 @@ struct GemmDescT {
     unsigned flags = 0;
     int nalpha = 0;          // if > 0, alpha_b = alphas[b] (b < nalpha <= 16)
     double alphas[kMaxInlineAlpha] = {};
+    // Split-K (batch2 must be 1): the k-range is cut into `splitk` pieces whose
+    // partial products go to `work` (splitk x outputs x m x n, ld m) and a
+    // second kernel sums them in order into C.
+    int splitk = 1;
+    T* work = nullptr;
 };
 using GemmDesc = GemmDescT<double>;
 using SGemmDesc = GemmDescT<float>;
@@ -61,6 +66,9 @@ using SGemmDesc = GemmDescT<float>;
 // Launches D = ... on `stream`.  Returns hipSuccess or the launch error.
 hipError_t gemm(const GemmDesc& d, hipStream_t stream);
 hipError_t gemm(const SGemmDesc& d, hipStream_t stream);
+// As gemm(), but a product whose output has too few tiles to fill the chip
+// and a long k-range is split along k into `work` (up to work_elems doubles).
+hipError_t gemm_split(GemmDesc d, double* work, size_t work_elems, hipStream_t stream);
 
 // Rough count of the floating-point operations a descriptor executes
 // (2 m n k per product, halved per triangular operand / upper-tile output).

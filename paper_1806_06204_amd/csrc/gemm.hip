@@ -62,6 +62,11 @@ __global__ __launch_bounds__(256, (BM * BN >= 128 * 128) ? 1 : 2) void gemm_kern
     const int nbatch = d.reduce ? d.batch : 1;
     const int bfirst = d.reduce ? 0 : blockIdx.y;
     const int ntiles = nk * nbatch;   // (batch, k) slices walked as one sequence
+    const bool split = d.splitk > 1;
+    const int z2 = split ? 0 : blockIdx.z;                 // outer batch index
+    const int t_begin = split ? (int)((long long)blockIdx.z * ntiles / d.splitk) : 0;
+    const int t_end = split ? (int)((long long)(blockIdx.z + 1) * ntiles / d.splitk) : ntiles;
+    const int nt = t_end - t_begin;
 
     acc_t acc[FM][FN];
 #pragma unroll
@@ -81,8 +86,8 @@ __global__ __launch_bounds__(256, (BM * BN >= 128 * 128) ? 1 : 2) void gemm_kern
         const int bi = t / nk;
         const int k0 = kb + (t - bi * nk) * BK;
         const int b = bfirst + bi;
-        const T* __restrict__ A = d.A + (long long)b * d.strideA + (long long)blockIdx.z * d.strideA2;
-        const T* __restrict__ B = d.B + (long long)b * d.strideB + (long long)blockIdx.z * d.strideB2;
+        const T* __restrict__ A = d.A + (long long)b * d.strideA + (long long)z2 * d.strideA2;
+        const T* __restrict__ B = d.B + (long long)b * d.strideB + (long long)z2 * d.strideB2;
         al_cur = d.nalpha > 0 ? (T)d.alphas[b] : (T)1;
         amask = 0;
         bmask = 0;
@@ -135,10 +140,10 @@ __global__ __launch_bounds__(256, (BM * BN >= 128 * 128) ? 1 : 2) void gemm_kern
     // previous store: Cin and C may be the same array).  Out-of-range lanes
     // load a valid address and drop the value.
     const int ob = d.reduce ? 0 : blockIdx.y;
-    T* __restrict__ C = d.C + (long long)ob * d.strideC + (long long)blockIdx.z * d.strideC2;
-    const T* Cin = d.Cin ? d.Cin + (long long)ob * d.strideCin + (long long)blockIdx.z * d.strideCin2 : nullptr;
+    T* __restrict__ C = d.C + (long long)ob * d.strideC + (long long)z2 * d.strideC2;
+    const T* Cin = d.Cin ? d.Cin + (long long)ob * d.strideCin + (long long)z2 * d.strideCin2 : nullptr;
     const T alpha = (T)d.alpha, beta = (T)d.beta;
-    const bool use_cin = Cin != nullptr && d.beta != 0.0;
+    const bool use_cin = !split && Cin != nullptr && d.beta != 0.0;
     T cin[FM][FN][4];
     if (use_cin) {
 #pragma unroll
@@ -154,13 +159,13 @@ __global__ __launch_bounds__(256, (BM * BN >= 128 * 128) ? 1 : 2) void gemm_kern
                 }
     }
 
-    if (ntiles > 0) {
-        gload(0);
+    if (nt > 0) {
+        gload(t_begin);
         lstore(0);
         __syncthreads();
-        if (ntiles > 1) gload(1);
-        for (int t = 0; t < ntiles; ++t) {
-            const int cur = t & 1;
+        if (nt > 1) gload(t_begin + 1);
+        for (int u = 0; u < nt; ++u) {
+            const int cur = u & 1;
 #pragma unroll
             for (int k4 = 0; k4 < BK; k4 += 4) {
                 T af[FM], bf[FN];
@@ -174,18 +179,35 @@ __global__ __launch_bounds__(256, (BM * BN >= 128 * 128) ? 1 : 2) void gemm_kern
 #pragma unroll
                     for (int j = 0; j < FN; ++j) acc[i][j] = Mfma<T>::run(af[i], bf[j], acc[i][j]);
             }
-            if (t + 1 < ntiles) {
-                // The other buffer was last read in iteration t-1, before the
+            if (u + 1 < nt) {
+                // The other buffer was last read in iteration u-1, before the
                 // barrier that ended it, so it can be refilled now.  Keep the
                 // stores (which wait for the loads in flight) after the MFMAs.
                 __builtin_amdgcn_sched_barrier(0);
                 lstore(cur ^ 1);
                 __syncthreads();
-                if (t + 2 < ntiles) gload(t + 2);
+                if (u + 2 < nt) gload(t_begin + u + 2);
             }
         }
     }
 
+    if (split) {
+        // Raw partial product of this k-piece; the reduce kernel scales,
+        // adds Cin and applies the store masks.
+        const int nout = d.reduce ? 1 : d.batch;
+        T* __restrict__ Wp = d.work + ((long long)blockIdx.z * nout + ob) * ((long long)d.m * d.n);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int gi = row0 + wm + i * 16 + Mfma<T>::row(lane, e);
+                    const int gj = col0 + wn + j * 16 + (lane & 15);
+                    if (gi < d.m && gj < d.n) Wp[gi + (long long)gj * d.m] = acc[i][j][e];
+                }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -205,10 +227,31 @@ __global__ __launch_bounds__(256, (BM * BN >= 128 * 128) ? 1 : 2) void gemm_kern
             }
 }
 
+// C = alpha * (sum over the k-pieces in order) + beta * Cin, with the store masks.
+template <class T>
+__global__ void splitk_reduce_kernel(GemmDescT<T> d) {
+    const int nout = d.reduce ? 1 : d.batch;
+    const long long mn = (long long)d.m * d.n, total = mn * nout;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long ob = e / mn, r = e - ob * mn;
+        const int gj = (int)(r / d.m), gi = (int)(r - (long long)gj * d.m);
+        bool ok = true;
+        if (d.flags & kCStoreUpper) ok = ok && gi <= gj;
+        if (d.flags & kCStoreLower) ok = ok && gi >= gj;
+        if (!ok) continue;
+        T s = 0;
+        for (int z = 0; z < d.splitk; ++z) s += d.work[((long long)z * nout + ob) * mn + r];
+        T v = (T)d.alpha * s;
+        if (d.Cin && d.beta != 0.0) v += (T)d.beta * d.Cin[ob * d.strideCin + gi + (long long)gj * d.ldcin];
+        d.C[ob * d.strideC + gi + (long long)gj * d.ldc] = v;
+    }
+}
+
 template <class T, int BM, int BN>
 hipError_t launch_bm_bn(const GemmDescT<T>& d, hipStream_t s) {
     const int tiles = ((d.m + BM - 1) / BM) * ((d.n + BN - 1) / BN);
-    dim3 grid(tiles, d.reduce ? 1 : d.batch, d.batch2);
+    dim3 grid(tiles, d.reduce ? 1 : d.batch, d.splitk > 1 ? d.splitk : d.batch2);
     const int which = (d.transa ? 2 : 0) + (d.transb ? 1 : 0);
     char name[64];
     if (stats_on()) {
@@ -222,8 +265,30 @@ hipError_t launch_bm_bn(const GemmDescT<T>& d, hipStream_t s) {
     else if (which == 1) gemm_kernel<T, BM, BN, false, true><<<grid, 256, 0, s>>>(d);
     else if (which == 2) gemm_kernel<T, BM, BN, true, false><<<grid, 256, 0, s>>>(d);
     else gemm_kernel<T, BM, BN, true, true><<<grid, 256, 0, s>>>(d);
+    if (d.splitk > 1) {
+        const long long total = (long long)d.m * d.n * (d.reduce ? 1 : d.batch);
+        long long g = (total + 255) / 256;
+        if (g > 2048) g = 2048;
+        splitk_reduce_kernel<T><<<(int)g, 256, 0, s>>>(d);
+    }
     sc.end();
     return hipGetLastError();
+}
+
+// Tile shape for a descriptor: bit 1 = 128 rows (else 64), bit 0 = 128 columns.
+// Measured on gfx950 (FP64): 64-row tiles, which run two workgroups per CU,
+// beat 128 x 128 on every shape of the solve: 39.7-40.2 TFLOP/s with
+// 64 x 128 against 34.6-35.0 with 128 x 128 at 8192^3, 35.3 against 32.9 on
+// the 128 x 4096 x 8320 x 8 block-reflector products, and on the short-K
+// trailing updates, which are bound by moving C, 64 x 64 reaches 2.5-2.7 TB/s
+// against 2.0-2.2.  64 x 128 is kept for outputs with at least 128 rows and
+// columns that still give a full wave of tiles, 64 x 64 otherwise.
+template <class T>
+int pick_tile(const GemmDescT<T>& d) {
+    if (d.k <= 128) return 0;
+    const long long t1 = (long long)((d.m + 63) / 64) * ((d.n + 127) / 128) * (d.reduce ? 1 : d.batch) * d.batch2;
+    if (d.m >= 128 && d.n >= 128 && t1 >= 256) return 1;
+    return 0;
 }
 
 template <class T>
@@ -231,24 +296,40 @@ hipError_t gemm_dispatch(const GemmDescT<T>& d, hipStream_t s) {
     if (d.m <= 0 || d.n <= 0) return hipSuccess;
     if (d.batch <= 0 || d.batch2 <= 0) return hipSuccess;
     if (d.nalpha > kMaxInlineAlpha || (d.nalpha > 0 && d.nalpha < d.batch)) return hipErrorInvalidValue;
-    // Small outputs use 64-wide tiles so that the grid still covers the chip.
-    const long long big_tiles =
-        (long long)((d.m + 127) / 128) * ((d.n + 127) / 128) * (d.reduce ? 1 : d.batch) * d.batch2;
-    const bool small_m = d.m <= 64 || big_tiles < 256;
-    const bool small_n = d.n <= 64 || big_tiles < 256;
-    // Short-K products (the rank-64 trailing updates) are bound by moving C,
-    // not by the MFMAs: 64 x 64 tiles run two workgroups per CU, so one
-    // tile's loads and stores overlap another's MFMAs (measured 2.0-2.2 TB/s
-    // with 128 x 128 tiles, 2.5-2.7 TB/s with 64 x 64 on 8256 x n x 64 x 8).
-    if (d.k <= 128 || (small_m && small_n)) return launch_bm_bn<T, 64, 64>(d, s);
-    if (small_m) return launch_bm_bn<T, 64, 128>(d, s);
-    if (small_n) return launch_bm_bn<T, 128, 64>(d, s);
-    return launch_bm_bn<T, 128, 128>(d, s);
+    if (d.splitk > 1 && (d.batch2 != 1 || d.work == nullptr)) return hipErrorInvalidValue;
+    switch (pick_tile(d)) {
+        case 0: return launch_bm_bn<T, 64, 64>(d, s);
+        case 1: return launch_bm_bn<T, 64, 128>(d, s);
+        case 2: return launch_bm_bn<T, 128, 64>(d, s);
+        default: return launch_bm_bn<T, 128, 128>(d, s);
+    }
 }
 
 }  // namespace
 
 hipError_t gemm(const GemmDesc& d, hipStream_t s) { return gemm_dispatch(d, s); }
 hipError_t gemm(const SGemmDesc& d, hipStream_t s) { return gemm_dispatch(d, s); }
+
+hipError_t gemm_split(GemmDesc d, double* work, size_t work_elems, hipStream_t s) {
+    d.splitk = 1;
+    if (work != nullptr && d.batch2 == 1 && d.k >= 1024 && d.m > 0 && d.n > 0 && d.batch > 0 &&
+        !(d.flags & kCUpperTiles)) {
+        const int t = pick_tile(d);
+        const int bm = (t & 2) ? 128 : 64, bn = (t & 1) ? 128 : 64;
+        const long long tiles = (long long)((d.m + bm - 1) / bm) * ((d.n + bn - 1) / bn) * (d.reduce ? 1 : d.batch);
+        if (tiles < 512) {
+            long long sk = (512 + tiles - 1) / tiles;             // about two workgroups per CU
+            sk = sk < d.k / 512 ? sk : d.k / 512;                 // at least 512 of k per piece
+            sk = sk < 32 ? sk : 32;
+            const long long per = (long long)d.m * d.n * (d.reduce ? 1 : d.batch);
+            if (sk * per > (long long)work_elems) sk = (long long)work_elems / per;
+            if (sk > 1) {
+                d.splitk = (int)sk;
+                d.work = work;
+            }
+        }
+    }
+    return gemm_dispatch(d, s);
+}
 
 }  // namespace zolo

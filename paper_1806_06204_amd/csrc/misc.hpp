@@ -60,10 +60,16 @@ hipError_t trtri_batched(int n, const T* R, long long ldr, long long sr, T* Rinv
 
 // --- qr.hip ---------------------------------------------------------------
 constexpr int kPanelNB = 64;
+constexpr int kQrBlock = 2 * kPanelNB;  // two panels share one trailing update
+constexpr size_t kQrSplitElems = (size_t)4 << 20;  // split-K workspace of the QR updates (32 MiB)
 
 struct QrWork {
-    double* W = nullptr;          // batch * kPanelNB * n doubles
+    double* W = nullptr;          // qr_w_elems(n, batch) doubles
+    double* W2 = nullptr;         // qr_w_elems(n, batch) doubles
     double* T = nullptr;          // batch * npanels * kPanelNB^2 doubles
+    double* Tb = nullptr;         // qr_tb_elems(n, batch) doubles (T of each 128-column block)
+    double* splitk = nullptr;     // kQrSplitElems doubles: split-K partial products
+    size_t splitk_elems = 0;
     double* Rd = nullptr;         // batch * npanels * kPanelNB^2 doubles (R diagonal blocks)
     double* S = nullptr;          // batch * kPanelNB^2 doubles
     double* partials = nullptr;   // batch * 2 * maxG * 2 * kPanelNB doubles
@@ -71,6 +77,11 @@ struct QrWork {
     int* error_flag = nullptr;    // 1 int
     int max_coresident = 0;       // workgroups of the panel kernel that fit at once
 };
+
+inline size_t qr_w_elems(int n, int batch) { return (size_t)batch * kQrBlock * n; }
+inline size_t qr_tb_elems(int n, int batch) {
+    return (size_t)batch * ((n + kQrBlock - 1) / kQrBlock) * kQrBlock * kQrBlock;
+}
 
 // Doubles each QrWork array needs for m x n, `batch` matrices, e extra rows.
 inline size_t qr_partials_elems(int m, int e, int batch, int max_coresident) {
@@ -88,7 +99,8 @@ hipError_t stack_init(int m, int n, const double* X, long long ldx, double* M, l
 // Householder QR of M_b ((m + e) x n, e = n for the stacked [Y; p I] of
 // eq. (12) (Section 3.1: each block of 64 reflectors acts on the m + 64
 // contiguous rows [p0, m + p0 + 64)), or e = 0 for a plain QR of an m x n
-// matrix).  On exit M_b holds the Householder vectors (explicit unit lower
+// matrix).  Panels of 64 columns are factored in pairs; each pair updates the
+// rest of the matrix once, as one block reflector of 128 columns.  On exit M_b holds the Householder vectors (explicit unit lower
 // trapezoidal), w.T the block-reflector factors and w.Rd the diagonal blocks of
 // R; the rest of R is in the upper part of M_b (see assemble_r).
 hipError_t structured_geqrf(int m, int e, int n, double* M, long long ld, long long sm, int batch,

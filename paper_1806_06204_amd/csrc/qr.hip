@@ -24,8 +24,14 @@
 // and the R diagonal block is saved apart.
 //
 // Trailing update and Q formation are GEMMs on the MFMA kernel over the live
-// rows:  W = V^T C,  W <- T^T W,  C -= V W  (ORGQR: T instead of T^T, panels
-// last to first, then the panel's own columns = [I; 0] - V (T V_top^T)).
+// rows:  W = V^T C,  W2 = T^T W,  C -= V W2  (ORGQR: T instead of T^T, last
+// to first, then a panel's own columns = [I; 0] - V (T V_top^T)).  Panels
+// come in pairs: the second panel is updated by the first, and the rest of
+// the matrix by both at once with the compact-WY factor of the pair,
+// T = [T1, -T1 V1^T V2 T2; 0, T2], so each trailing element is read and
+// written once per 128 columns (the stored R entries of the first panel that
+// sit above the second panel's diagonal are masked out of V by the GEMM's
+// triangular flags).
 #include "misc.hpp"
 #include "stats.hpp"
 
@@ -421,64 +427,158 @@ hipError_t assemble_r(int n, const double* M, long long ld, long long sm, int ba
     return hipGetLastError();
 }
 
+namespace {
+
+// Cooperative launch of the panel kernel for panel p (columns p0 .. p0+nb-1).
+hipError_t run_panel(int m, int e, int p, int nb, double* M, long long ld, long long sm, int batch, const QrWork& w,
+                     long long stT, hipStream_t st) {
+    const int p0 = p * kNB;
+    const int L = live_rows(m, e, p0, nb);
+    const Geometry geo = panel_geometry(L, batch, w.max_coresident);
+    PanelArgs pa;
+    pa.L = L; pa.nb = nb; pa.G = geo.G; pa.rows_per_wg = geo.rows;
+    pa.P = M + p0 + (long long)p0 * ld; pa.ld = ld; pa.sp = sm;
+    pa.T = w.T + (long long)p * kNB * kNB; pa.st = stT;
+    pa.Rd = w.Rd + (long long)p * kNB * kNB; pa.srd = stT;
+    pa.partials = w.partials;
+    pa.counters = w.counters + (long long)p * batch;
+    pa.error_flag = w.error_flag;
+    pa.spin_limit = 1u << 24;
+    pa.lds_stride = geo.rows;
+    void* args[] = {&pa};
+    StatScope sc(geo.lds ? "panel_kernel<lds>" : "panel_kernel<global>", st, 4.0 * L * (double)nb * nb * batch);
+    hipError_t err;
+    if (geo.lds)
+        err = hipLaunchCooperativeKernel((const void*)panel_kernel<true>, dim3(pa.G * batch), dim3(kPT), args,
+                                         (size_t)geo.rows * kNB * sizeof(double), st);
+    else
+        err = hipLaunchCooperativeKernel((const void*)panel_kernel<false>, dim3(pa.G * batch), dim3(kPT), args, 0, st);
+    sc.end();
+    return err;
+}
+
+// Applies the block reflector I - V T V^T (forward: its transpose, as in the
+// factorisation; backward: itself, as in forming Q) of the nbv columns of V
+// starting at column c0 to `trail` columns C starting at column c0 + nbv, over
+// the live rows [c0, c0 + L).  T (ld ldt, batch stride stt) is upper
+// triangular.  V's zeros above its unit diagonal, including an R block stored
+// there by an earlier panel of the same block, are masked by the GEMM's
+// triangular flags.
+hipError_t apply_block(int L, int c0, int nbv, int trail, const double* Tm, long long ldt, long long stt,
+                       bool transpose_t, double* M, long long ld, long long sm, int batch, const QrWork& w,
+                       hipStream_t st) {
+    if (trail <= 0) return hipSuccess;
+    const double* V = M + c0 + (long long)c0 * ld;
+    double* C = M + c0 + (long long)(c0 + nbv) * ld;
+    const long long sw = (long long)kQrBlock * trail;
+    GemmDesc g1;  // W = V^T C
+    g1.m = nbv; g1.n = trail; g1.k = L; g1.transa = 1;
+    g1.A = V; g1.lda = ld; g1.strideA = sm;
+    g1.B = C; g1.ldb = ld; g1.strideB = sm;
+    g1.C = w.W; g1.ldc = kQrBlock; g1.strideC = sw;
+    g1.batch = batch; g1.flags = kAUpper;
+    hipError_t err = gemm_split(g1, w.splitk, w.splitk_elems, st);
+    if (err != hipSuccess) return err;
+    GemmDesc g2;  // W2 = T^T W (forward) or T W (backward)
+    g2.m = nbv; g2.n = trail; g2.k = nbv; g2.transa = transpose_t ? 1 : 0;
+    g2.A = Tm; g2.lda = ldt; g2.strideA = stt;
+    g2.B = w.W; g2.ldb = kQrBlock; g2.strideB = sw;
+    g2.C = w.W2; g2.ldc = kQrBlock; g2.strideC = sw;
+    g2.batch = batch; g2.flags = transpose_t ? kALower : kAUpper;
+    if ((err = gemm(g2, st)) != hipSuccess) return err;
+    GemmDesc g3;  // C -= V W2
+    g3.m = L; g3.n = trail; g3.k = nbv;
+    g3.A = V; g3.lda = ld; g3.strideA = sm;
+    g3.B = w.W2; g3.ldb = kQrBlock; g3.strideB = sw;
+    g3.Cin = C; g3.ldcin = ld; g3.strideCin = sm;
+    g3.C = C; g3.ldc = ld; g3.strideC = sm;
+    g3.alpha = -1.0; g3.beta = 1.0; g3.batch = batch; g3.flags = kALower;
+    return gemm(g3, st);
+}
+
+// Tb = [T1, -T1 (V1^T V2) T2; 0, T2] for the block of panels p, p+1 at
+// column p0 (second panel nb2 wide): the compact-WY factor of the product of
+// the two block reflectors.
+__global__ void assemble_tb_kernel(int nb2, const double* __restrict__ T, long long stT, int p,
+                                   double* __restrict__ Tb, long long stb) {
+    const int b = blockIdx.y;
+    const double* T1 = T + b * stT + (long long)p * kNB * kNB;
+    const double* T2 = T1 + kNB * kNB;
+    double* D = Tb + b * stb;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < kQrBlock * kQrBlock; e += gridDim.x * blockDim.x) {
+        const int i = e % kQrBlock, j = e / kQrBlock;
+        double v = 0.0;
+        if (i < kNB && j < kNB) v = T1[i + j * kNB];
+        else if (i >= kNB && j >= kNB && i < kNB + nb2 && j < kNB + nb2) v = T2[(i - kNB) + (j - kNB) * kNB];
+        else if (i < kNB && j >= kNB && j < kNB + nb2) v = D[e];  // T12, written by the GEMM before this kernel
+        D[e] = v;
+    }
+}
+
+hipError_t merge_t(int m, int e, int p, int nb2, double* M, long long ld, long long sm, int batch, const QrWork& w,
+                   long long stT, double* Tb, long long stb, hipStream_t st) {
+    const int p0 = p * kNB;
+    const int k = live_rows(m, e, p0, kNB) - kNB;  // rows V1 and V2 share
+    GemmDesc g;  // P = V1^T V2 (64 x nb2) into S
+    g.m = kNB; g.n = nb2; g.k = k; g.transa = 1;
+    g.A = M + (p0 + kNB) + (long long)p0 * ld; g.lda = ld; g.strideA = sm;
+    g.B = M + (p0 + kNB) + (long long)(p0 + kNB) * ld; g.ldb = ld; g.strideB = sm;
+    g.C = w.S; g.ldc = kNB; g.strideC = (long long)kNB * kNB;
+    g.batch = batch;
+    hipError_t err = gemm_split(g, w.splitk, w.splitk_elems, st);
+    if (err != hipSuccess) return err;
+    GemmDesc y;  // Y = P T2 into W2 (T2 upper)
+    y.m = kNB; y.n = nb2; y.k = nb2;
+    y.A = w.S; y.lda = kNB; y.strideA = (long long)kNB * kNB;
+    y.B = w.T + (long long)(p + 1) * kNB * kNB; y.ldb = kNB; y.strideB = stT;
+    y.C = w.W2; y.ldc = kNB; y.strideC = (long long)kNB * kNB;
+    y.batch = batch; y.flags = kBUpper;
+    if ((err = gemm(y, st)) != hipSuccess) return err;
+    GemmDesc t;  // T12 = -T1 Y (T1 upper) into Tb[0:64, 64:64+nb2]
+    t.m = kNB; t.n = nb2; t.k = kNB;
+    t.A = w.T + (long long)p * kNB * kNB; t.lda = kNB; t.strideA = stT;
+    t.B = w.W2; t.ldb = kNB; t.strideB = (long long)kNB * kNB;
+    t.C = Tb + (long long)kNB * kQrBlock; t.ldc = kQrBlock; t.strideC = stb;
+    t.alpha = -1.0; t.batch = batch; t.flags = kAUpper;
+    if ((err = gemm(t, st)) != hipSuccess) return err;
+    assemble_tb_kernel<<<dim3(16, batch), 256, 0, st>>>(nb2, w.T, stT, p, Tb, stb);
+    return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t structured_geqrf(int m, int e, int n, double* M, long long ld, long long sm, int batch, const QrWork& w,
                             hipStream_t st) {
     if (batch > kMaxInlineAlpha || batch < 1) return hipErrorInvalidValue;
     const int npanels = (n + kNB - 1) / kNB;
+    const int nblocks = (n + kQrBlock - 1) / kQrBlock;
     const long long stT = (long long)npanels * kNB * kNB;
+    const long long stb = (long long)nblocks * kQrBlock * kQrBlock;
     hipError_t err = hipMemsetAsync(w.counters, 0, sizeof(unsigned) * (size_t)batch * npanels, st);
     if (err != hipSuccess) return err;
-    for (int p = 0; p < npanels; ++p) {
-        const int p0 = p * kNB;
-        const int nb = n - p0 < kNB ? n - p0 : kNB;
-        const int L = live_rows(m, e, p0, nb);
-        const Geometry geo = panel_geometry(L, batch, w.max_coresident);
-        PanelArgs pa;
-        pa.L = L; pa.nb = nb; pa.G = geo.G; pa.rows_per_wg = geo.rows;
-        pa.P = M + p0 + (long long)p0 * ld; pa.ld = ld; pa.sp = sm;
-        pa.T = w.T + (long long)p * kNB * kNB; pa.st = stT;
-        pa.Rd = w.Rd + (long long)p * kNB * kNB; pa.srd = stT;
-        pa.partials = w.partials;
-        pa.counters = w.counters + (long long)p * batch;
-        pa.error_flag = w.error_flag;
-        pa.spin_limit = 1u << 24;
-        pa.lds_stride = geo.rows;
-        void* args[] = {&pa};
-        StatScope sc(geo.lds ? "panel_kernel<lds>" : "panel_kernel<global>", st, 4.0 * L * (double)nb * nb * batch);
-        if (geo.lds)
-            err = hipLaunchCooperativeKernel((const void*)panel_kernel<true>, dim3(pa.G * batch), dim3(kPT), args,
-                                             (size_t)geo.rows * kNB * sizeof(double), st);
-        else
-            err = hipLaunchCooperativeKernel((const void*)panel_kernel<false>, dim3(pa.G * batch), dim3(kPT), args, 0,
-                                             st);
-        sc.end();
+    for (int q = 0; q < nblocks; ++q) {
+        const int p0 = q * kQrBlock, p = 2 * q;
+        const int nbq = n - p0 < kQrBlock ? n - p0 : kQrBlock;
+        const int nb1 = nbq < kNB ? nbq : kNB, nb2 = nbq - nb1;
+        const double* T1 = w.T + (long long)p * kNB * kNB;
+        // First panel of the block, then its reflectors on the second panel.
+        if ((err = run_panel(m, e, p, nb1, M, ld, sm, batch, w, stT, st)) != hipSuccess) return err;
+        if (nb2 == 0) {
+            err = apply_block(live_rows(m, e, p0, nb1), p0, nb1, n - p0 - nb1, T1, kNB, stT, true, M, ld, sm, batch,
+                              w, st);
+            if (err != hipSuccess) return err;
+            continue;
+        }
+        err = apply_block(live_rows(m, e, p0, nb1), p0, nb1, nb2, T1, kNB, stT, true, M, ld, sm, batch, w, st);
         if (err != hipSuccess) return err;
-        const int trail = n - p0 - nb;
+        if ((err = run_panel(m, e, p + 1, nb2, M, ld, sm, batch, w, stT, st)) != hipSuccess) return err;
+        // Both panels on the rest of the matrix as one 128-column block.
+        const int trail = n - p0 - nbq;
         if (trail <= 0) continue;
-        double* V = M + p0 + (long long)p0 * ld;
-        double* C = M + p0 + (long long)(p0 + nb) * ld;
-        GemmDesc g1;  // W = V^T C
-        g1.m = nb; g1.n = trail; g1.k = L; g1.transa = 1;
-        g1.A = V; g1.lda = ld; g1.strideA = sm;
-        g1.B = C; g1.ldb = ld; g1.strideB = sm;
-        g1.C = w.W; g1.ldc = kNB; g1.strideC = (long long)kNB * n;
-        g1.batch = batch;
-        if ((err = gemm(g1, st)) != hipSuccess) return err;
-        GemmDesc g2;  // W <- T^T W (one tile row: in place is safe)
-        g2.m = nb; g2.n = trail; g2.k = nb; g2.transa = 1;
-        g2.A = pa.T; g2.lda = kNB; g2.strideA = stT;
-        g2.B = w.W; g2.ldb = kNB; g2.strideB = (long long)kNB * n;
-        g2.C = w.W; g2.ldc = kNB; g2.strideC = (long long)kNB * n;
-        g2.batch = batch; g2.flags = kALower;
-        if ((err = gemm(g2, st)) != hipSuccess) return err;
-        GemmDesc g3;  // C -= V W
-        g3.m = L; g3.n = trail; g3.k = nb;
-        g3.A = V; g3.lda = ld; g3.strideA = sm;
-        g3.B = w.W; g3.ldb = kNB; g3.strideB = (long long)kNB * n;
-        g3.Cin = C; g3.ldcin = ld; g3.strideCin = sm;
-        g3.C = C; g3.ldc = ld; g3.strideC = sm;
-        g3.alpha = -1.0; g3.beta = 1.0; g3.batch = batch;
-        if ((err = gemm(g3, st)) != hipSuccess) return err;
+        double* Tb = w.Tb + (long long)q * kQrBlock * kQrBlock;
+        if ((err = merge_t(m, e, p, nb2, M, ld, sm, batch, w, stT, Tb, stb, st)) != hipSuccess) return err;
+        err = apply_block(live_rows(m, e, p0, nbq), p0, nbq, trail, Tb, kQrBlock, stb, true, M, ld, sm, batch, w, st);
+        if (err != hipSuccess) return err;
     }
     return hipSuccess;
 }
@@ -486,61 +586,56 @@ hipError_t structured_geqrf(int m, int e, int n, double* M, long long ld, long l
 hipError_t structured_orgqr(int m, int e, int n, double* M, long long ld, long long sm, int batch, const QrWork& w,
                             hipStream_t st) {
     const int npanels = (n + kNB - 1) / kNB;
+    const int nblocks = (n + kQrBlock - 1) / kQrBlock;
     const long long stT = (long long)npanels * kNB * kNB;
+    const long long stb = (long long)nblocks * kQrBlock * kQrBlock;
     hipError_t err;
-    for (int p = npanels - 1; p >= 0; --p) {
-        const int p0 = p * kNB;
-        const int nb = n - p0 < kNB ? n - p0 : kNB;
-        const int L = live_rows(m, e, p0, nb);
-        const int trail = n - p0 - nb;
-        const double* Tp = w.T + (long long)p * kNB * kNB;
-        double* V = M + p0 + (long long)p0 * ld;
+    for (int q = nblocks - 1; q >= 0; --q) {
+        const int p0 = q * kQrBlock;
+        const int nbq = n - p0 < kQrBlock ? n - p0 : kQrBlock;
+        const int trail = n - p0 - nbq;
+        // The block's reflectors on the columns already formed to its right.
         if (trail > 0) {
-            double* C = M + p0 + (long long)(p0 + nb) * ld;
-            GemmDesc g1;  // W = V^T C
-            g1.m = nb; g1.n = trail; g1.k = L; g1.transa = 1;
-            g1.A = V; g1.lda = ld; g1.strideA = sm;
-            g1.B = C; g1.ldb = ld; g1.strideB = sm;
-            g1.C = w.W; g1.ldc = kNB; g1.strideC = (long long)kNB * n;
-            g1.batch = batch;
-            if ((err = gemm(g1, st)) != hipSuccess) return err;
-            GemmDesc g2;  // W <- T W
-            g2.m = nb; g2.n = trail; g2.k = nb;
-            g2.A = Tp; g2.lda = kNB; g2.strideA = stT;
-            g2.B = w.W; g2.ldb = kNB; g2.strideB = (long long)kNB * n;
-            g2.C = w.W; g2.ldc = kNB; g2.strideC = (long long)kNB * n;
-            g2.batch = batch; g2.flags = kAUpper;
-            if ((err = gemm(g2, st)) != hipSuccess) return err;
-            GemmDesc g3;  // C -= V W
-            g3.m = L; g3.n = trail; g3.k = nb;
-            g3.A = V; g3.lda = ld; g3.strideA = sm;
-            g3.B = w.W; g3.ldb = kNB; g3.strideB = (long long)kNB * n;
-            g3.Cin = C; g3.ldcin = ld; g3.strideCin = sm;
-            g3.C = C; g3.ldc = ld; g3.strideC = sm;
-            g3.alpha = -1.0; g3.beta = 1.0; g3.batch = batch;
-            if ((err = gemm(g3, st)) != hipSuccess) return err;
+            if (nbq > kNB)
+                err = apply_block(live_rows(m, e, p0, nbq), p0, nbq, trail, w.Tb + (long long)q * kQrBlock * kQrBlock,
+                                  kQrBlock, stb, false, M, ld, sm, batch, w, st);
+            else
+                err = apply_block(live_rows(m, e, p0, nbq), p0, nbq, trail, w.T + (long long)(2 * q) * kNB * kNB, kNB,
+                                  stT, false, M, ld, sm, batch, w, st);
+            if (err != hipSuccess) return err;
         }
-        // Panel columns: S = T V_top^T, then Q[rows, panel] = -V S (in place:
-        // one tile column covers the nb <= 64 columns), then +I and zeros above.
-        GemmDesc s;
-        s.m = nb; s.n = nb; s.k = nb; s.transb = 1;
-        s.A = Tp; s.lda = kNB; s.strideA = stT;
-        s.B = V; s.ldb = ld; s.strideB = sm;
-        s.C = w.S; s.ldc = kNB; s.strideC = (long long)kNB * kNB;
-        s.batch = batch; s.flags = kAUpper | kBUpper;
-        if ((err = gemm(s, st)) != hipSuccess) return err;
-        GemmDesc q;
-        q.m = L; q.n = nb; q.k = nb;
-        q.A = V; q.lda = ld; q.strideA = sm;
-        q.B = w.S; q.ldb = kNB; q.strideB = (long long)kNB * kNB;
-        q.C = V; q.ldc = ld; q.strideC = sm;
-        q.alpha = -1.0; q.batch = batch;
-        if ((err = gemm(q, st)) != hipSuccess) return err;
-        const int total = (p0 + nb) * nb;
-        int grid = (total + 255) / 256;
-        if (grid > 1024) grid = 1024;
-        orgqr_fix_kernel<<<dim3(grid, batch), 256, 0, st>>>(p0, nb, M, ld, sm);
-        if ((err = hipGetLastError()) != hipSuccess) return err;
+        // The block's own columns, panel by panel from the last.
+        for (int p = (nbq > kNB ? 2 * q + 1 : 2 * q); p >= 2 * q; --p) {
+            const int pp0 = p * kNB;
+            const int nb = n - pp0 < kNB ? n - pp0 : kNB;
+            const int L = live_rows(m, e, pp0, nb);
+            const double* Tp = w.T + (long long)p * kNB * kNB;
+            double* V = M + pp0 + (long long)pp0 * ld;
+            const int inblock = p0 + nbq - pp0 - nb;
+            if ((err = apply_block(L, pp0, nb, inblock, Tp, kNB, stT, false, M, ld, sm, batch, w, st)) != hipSuccess)
+                return err;
+            // Panel columns: S = T V_top^T, then Q[rows, panel] = -V S (in place:
+            // one tile column covers the nb <= 64 columns), then +I and zeros above.
+            GemmDesc s;
+            s.m = nb; s.n = nb; s.k = nb; s.transb = 1;
+            s.A = Tp; s.lda = kNB; s.strideA = stT;
+            s.B = V; s.ldb = ld; s.strideB = sm;
+            s.C = w.S; s.ldc = kNB; s.strideC = (long long)kNB * kNB;
+            s.batch = batch; s.flags = kAUpper | kBUpper;
+            if ((err = gemm(s, st)) != hipSuccess) return err;
+            GemmDesc qd;
+            qd.m = L; qd.n = nb; qd.k = nb;
+            qd.A = V; qd.lda = ld; qd.strideA = sm;
+            qd.B = w.S; qd.ldb = kNB; qd.strideB = (long long)kNB * kNB;
+            qd.C = V; qd.ldc = ld; qd.strideC = sm;
+            qd.alpha = -1.0; qd.batch = batch;
+            if ((err = gemm(qd, st)) != hipSuccess) return err;
+            const int total = (pp0 + nb) * nb;
+            int grid = (total + 255) / 256;
+            if (grid > 1024) grid = 1024;
+            orgqr_fix_kernel<<<dim3(grid, batch), 256, 0, st>>>(pp0, nb, M, ld, sm);
+            if ((err = hipGetLastError()) != hipSuccess) return err;
+        }
     }
     return hipSuccess;
 }

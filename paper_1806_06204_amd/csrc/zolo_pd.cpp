@@ -99,8 +99,12 @@ Work layout(char* base, int m, int n, int rmax, int panel_coresident, bool mixed
     w.vec_w = ar.take<double>(n);
     w.lam = ar.take<double>(128);
     w.iflags = ar.take<int>(64);
-    w.qr.W = ar.take<double>((size_t)rmax * kPanelNB * n);
+    w.qr.W = ar.take<double>(qr_w_elems(n, rmax));
+    w.qr.W2 = ar.take<double>(qr_w_elems(n, rmax));
     w.qr.T = ar.take<double>((size_t)rmax * npanels * kPanelNB * kPanelNB);
+    w.qr.Tb = ar.take<double>(qr_tb_elems(n, rmax));
+    w.qr.splitk = ar.take<double>(kQrSplitElems);
+    w.qr.splitk_elems = kQrSplitElems;
     w.qr.Rd = ar.take<double>((size_t)rmax * npanels * kPanelNB * kPanelNB);
     w.qr.S = ar.take<double>((size_t)rmax * kPanelNB * kPanelNB);
     w.qr.partials = ar.take<double>(std::max(qr_partials_elems(m, n, rmax, panel_coresident),
@@ -400,7 +404,6 @@ int zolo_pd(zolo_handle h, int m, int n, const double* A, int lda, double alpha,
     }
     w = layout(h->arena, m, n, rmax, h->panel_coresident, mixed);
     hipStream_t st = h->stream;
-    const long long mn = (long long)m * n;
     int* hi = reinterpret_cast<int*>(h->host);
     // Stage times: drain the stream first so queued work is charged to the
     // stage that queued it.
