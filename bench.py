@@ -107,11 +107,11 @@ def bench_batched(args):
     ls = [1.0 / sp["kappa"] for sp in specs]
     z = zolo.Zolo()
     for _ in range(args.warmup):
-        z.pd_batched(mats, alphas=[1.0] * len(mats), ls=ls)
+        z.pd_batched(mats, alphas=[1.0] * len(mats), ls=ls, batch_streams=args.batch_streams)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        _, _, infos = z.pd_batched(mats, alphas=[1.0] * len(mats), ls=ls)
+        _, _, infos = z.pd_batched(mats, alphas=[1.0] * len(mats), ls=ls, batch_streams=args.batch_streams)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     fl = sum(paper_flops(sp["m"], sp["n"], inf["r"], inf["kinds"], 1 if inf["orth_check"] >= 0 else 0)
@@ -125,7 +125,8 @@ def bench_batched(args):
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"{len(specs)} matrices, n~U[64,1024], m~U[n,2n], log10 kappa~U[2,12], "
-                                  "l exact, r by the two-iteration policy", "count": len(specs)},
+                                  "l exact, r by the two-iteration policy", "count": len(specs),
+                      "batch_streams": args.batch_streams or 4},
            "matrices_per_s": len(specs) / dt,
            "r_histogram": {str(k): sum(1 for i in infos if i["r"] == k) for k in range(1, 9)},
            "max_bwd_err_sampled": max(e[0] for e in errs), "max_orth_err_sampled": max(e[1] for e in errs),
@@ -284,6 +285,8 @@ def main():
     ap.add_argument("--train-count", type=int, default=100000)
     ap.add_argument("--precision-study", action="store_true",
                     help="instead: FP64 vs mixed at kappa 1e4/1e8/1e12 (use with --r 3)")
+    ap.add_argument("--batch-streams", type=int, default=0,
+                    help="with --batched: solves run at once (0: the library default, 4)")
     ap.add_argument("--batched", type=int, default=0,
                     help="instead: Zolo-PD of this many uneven matrices (n in [64,1024], m in [n,2n], "
                          "kappa log-uniform in [1e2,1e12]) in one zolo_pd_batched call")

@@ -96,7 +96,12 @@ typedef struct {
                             condition estimate is used.  Either way the
                             verified stop rule judges the result: an l above
                             sigma_min costs iterations, not accuracy. */
-    int reserved[8];
+    int batch_streams;   /* zolo_pd_batched only: number of solves run at once,
+                            each on its own stream and host thread (0: 4; 1:
+                            one after another on the handle's stream).  Their
+                            cooperative panel launches share one stream, so
+                            at most one panel is in flight at any time. */
+    int reserved[7];
 } zolo_opts;
 
 /* Per-call report. */

@@ -12,7 +12,8 @@
  * Cin when beta != 0, and C; zero where a kernel does not model it).  These
  * give the measured rate of a kernel as work / time, the per-stage profile of
  * Table 7 of the paper at kernel granularity.
- * Statistics are process-wide (all handles) and not thread safe.
+ * Statistics are process-wide (all handles); the calls and the recording are
+ * serialised by one lock, so concurrent solves may record into them.
  */
 #ifndef ZOLO_STATS_H
 #define ZOLO_STATS_H

@@ -14,4 +14,9 @@ struct zolo_handle_s {
     double* host = nullptr;  // pinned scalars for read-back
     int panel_coresident = 0;
     float* est = nullptr;    // learned l/r estimator parameters (zolo_set_estimator)
+    // Worker handles of zolo_pd_batched: cooperative panel launches go to the
+    // shared panel stream (one panel in flight at a time across workers),
+    // ordered against this handle's stream by the two events.
+    hipStream_t panel_stream = nullptr;
+    hipEvent_t ev_ready = nullptr, ev_done = nullptr;
 };

@@ -70,6 +70,8 @@ struct QrWork {
     double* Tb = nullptr;         // qr_tb_elems(n, batch) doubles (T of each 128-column block)
     double* splitk = nullptr;     // kQrSplitElems doubles: split-K partial products
     size_t splitk_elems = 0;
+    hipStream_t panel_stream = nullptr;        // non-null: launch panels there (see run_panel)
+    hipEvent_t ev_ready = nullptr, ev_done = nullptr;
     double* Rd = nullptr;         // batch * npanels * kPanelNB^2 doubles (R diagonal blocks)
     double* S = nullptr;          // batch * kPanelNB^2 doubles
     double* partials = nullptr;   // batch * 2 * maxG * 2 * kPanelNB doubles

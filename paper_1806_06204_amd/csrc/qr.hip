@@ -37,6 +37,7 @@
 
 #include <cstdlib>
 #include <map>
+#include <mutex>
 
 namespace zolo {
 namespace {
@@ -148,48 +149,58 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
         // that wait another workgroup can see the counter and read a stale
         // partial.  No release/acquire fences: those would write back or
         // invalidate the whole L2 on every column.
-        double* part = a.partials + (((long long)b * 2 + (k & 1)) * a.G + g) * (2 * kNB);
-        if (tid < nb) {
-            __hip_atomic_store(&part[tid], s_w[tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&part[kNB + tid], s_w[kNB + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
-        }
-        __syncthreads();
-        if (tid == 0) {
-            __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const unsigned target = (unsigned)(k + 1) * (unsigned)a.G;
-            unsigned spins = 0;
-            while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                if (++spins > a.spin_limit) {
-                    atomicOr(a.error_flag, 1);
-                    break;
+        // One workgroup per matrix: its own sums are the totals.
+        if (a.G == 1) {
+            if (tid < nb) {
+                s_d[tid] = s_w[tid];
+                s_pr[tid] = s_w[kNB + tid];
+            }
+            __syncthreads();
+        } else {
+            double* part = a.partials + (((long long)b * 2 + (k & 1)) * a.G + g) * (2 * kNB);
+            if (tid < nb) {
+                __hip_atomic_store(&part[tid], s_w[tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&part[kNB + tid], s_w[kNB + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+            }
+            __syncthreads();
+            if (tid == 0) {
+                __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const unsigned target = (unsigned)(k + 1) * (unsigned)a.G;
+                unsigned spins = 0;
+                while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                    if (++spins > a.spin_limit) {
+                        atomicOr(a.error_flag, 1);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
                 }
-                __builtin_amdgcn_s_sleep(1);
             }
-        }
-        __syncthreads();
-        if (tid < 2 * nb) {
-            // Coherent loads have memory latency: issue them eight at a time
-            // and add in a fixed order.
-            const int idx = tid < nb ? tid : kNB + (tid - nb);
-            const double* pb = a.partials + ((long long)b * 2 + (k & 1)) * a.G * (2 * kNB);
-            double sum = 0.0;
-            int gg = 0;
-            for (; gg + 8 <= a.G; gg += 8) {
-                double v[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    v[u] = __hip_atomic_load(&pb[(gg + u) * (2 * kNB) + idx], __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-#pragma unroll
-                for (int u = 0; u < 8; ++u) sum += v[u];
+            __syncthreads();
+            if (tid < 2 * nb) {
+                // Coherent loads have memory latency: issue them eight at a time
+                // and add in a fixed order.
+                const int idx = tid < nb ? tid : kNB + (tid - nb);
+                const double* pb = a.partials + ((long long)b * 2 + (k & 1)) * a.G * (2 * kNB);
+                double sum = 0.0;
+                int gg = 0;
+                for (; gg + 8 <= a.G; gg += 8) {
+                    double v[8];
+    #pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        v[u] = __hip_atomic_load(&pb[(gg + u) * (2 * kNB) + idx], __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    #pragma unroll
+                    for (int u = 0; u < 8; ++u) sum += v[u];
+                }
+                for (; gg < a.G; ++gg)
+                    sum += __hip_atomic_load(&pb[gg * (2 * kNB) + idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (tid < nb) s_d[tid] = sum;
+                else s_pr[tid - nb] = sum;
             }
-            for (; gg < a.G; ++gg)
-                sum += __hip_atomic_load(&pb[gg * (2 * kNB) + idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (tid < nb) s_d[tid] = sum;
-            else s_pr[tid - nb] = sum;
+            __syncthreads();
+
         }
-        __syncthreads();
 
         // Phase C: reflector k on x = [alpha; below], beta = -sign(alpha) |x|,
         // v = [1; below / (alpha - beta)]  (no cancellation in alpha - beta).
@@ -352,6 +363,8 @@ int cu_count() {
 // Co-resident workgroups of the LDS panel kernel with an R-row slab.
 int lds_coresident(int R) {
     static std::map<int, int> cache;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lock(mu);
     auto it = cache.find(R);
     if (it != cache.end()) return it->second;
     int per_cu = 0;
@@ -446,14 +459,38 @@ hipError_t run_panel(int m, int e, int p, int nb, double* M, long long ld, long 
     pa.spin_limit = 1u << 24;
     pa.lds_stride = geo.rows;
     void* args[] = {&pa};
-    StatScope sc(geo.lds ? "panel_kernel<lds>" : "panel_kernel<global>", st, 4.0 * L * (double)nb * nb * batch);
     hipError_t err;
+    if (geo.G == 1) {
+        // One workgroup per matrix needs no co-residency: an ordinary launch
+        // on the solve's own stream, free to overlap other solves.
+        StatScope sc(geo.lds ? "panel_kernel<lds>" : "panel_kernel<global>", st, 4.0 * L * (double)nb * nb * batch);
+        if (geo.lds)
+            panel_kernel<true><<<batch, kPT, (size_t)geo.rows * kNB * sizeof(double), st>>>(pa);
+        else
+            panel_kernel<false><<<batch, kPT, 0, st>>>(pa);
+        sc.end();
+        return hipGetLastError();
+    }
+    // Several solves at once (zolo_pd_batched): every cooperative panel goes
+    // to one shared stream, so two panels never wait for each other's
+    // workgroups to become resident; events order it against this solve.
+    hipStream_t ps = st;
+    if (w.panel_stream && w.panel_stream != st) {
+        ps = w.panel_stream;
+        if ((err = hipEventRecord(w.ev_ready, st)) != hipSuccess) return err;
+        if ((err = hipStreamWaitEvent(ps, w.ev_ready, 0)) != hipSuccess) return err;
+    }
+    StatScope sc(geo.lds ? "panel_kernel<lds>" : "panel_kernel<global>", ps, 4.0 * L * (double)nb * nb * batch);
     if (geo.lds)
         err = hipLaunchCooperativeKernel((const void*)panel_kernel<true>, dim3(pa.G * batch), dim3(kPT), args,
-                                         (size_t)geo.rows * kNB * sizeof(double), st);
+                                         (size_t)geo.rows * kNB * sizeof(double), ps);
     else
-        err = hipLaunchCooperativeKernel((const void*)panel_kernel<false>, dim3(pa.G * batch), dim3(kPT), args, 0, st);
+        err = hipLaunchCooperativeKernel((const void*)panel_kernel<false>, dim3(pa.G * batch), dim3(kPT), args, 0, ps);
     sc.end();
+    if (err == hipSuccess && ps != st) {
+        if ((err = hipEventRecord(w.ev_done, ps)) != hipSuccess) return err;
+        err = hipStreamWaitEvent(st, w.ev_done, 0);
+    }
     return err;
 }
 

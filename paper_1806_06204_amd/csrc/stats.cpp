@@ -2,6 +2,7 @@
 #include "stats.hpp"
 
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -26,6 +27,7 @@ struct Pending {
 constexpr int kPairs = 8192;
 
 struct Registry {
+    std::mutex mu;   // the public entry points and StatScope hold it
     bool on = false;
     std::vector<Entry> entries;
     std::vector<hipEvent_t> ev0, ev1;
@@ -77,6 +79,7 @@ bool stats_on() { return reg().on; }
 StatScope::StatScope(const char* name, hipStream_t st, double flops, double bytes) {
     Registry& r = reg();
     if (!r.on) return;
+    std::lock_guard<std::mutex> lock(r.mu);
     slot_ = r.slot_for(name);
     r.entries[slot_].launches += 1;
     r.entries[slot_].flops += flops;
@@ -89,6 +92,7 @@ StatScope::StatScope(const char* name, hipStream_t st, double flops, double byte
 void StatScope::end() {
     Registry& r = reg();
     if (slot_ < 0 || pair_ < 0) return;
+    std::lock_guard<std::mutex> lock(r.mu);
     if (hipEventRecord(r.ev1[pair_], st_) == hipSuccess) r.pending.push_back(Pending{slot_, pair_});
     slot_ = -1;
 }
@@ -104,16 +108,22 @@ int zolo_stats_enable(int on) {
 
 int zolo_stats_reset(void) {
     zolo::Registry& r = zolo::reg();
+    std::lock_guard<std::mutex> lock(r.mu);
     r.collect();
     r.entries.clear();
     return 0;
 }
 
-int zolo_stats_count(void) { return (int)zolo::reg().entries.size(); }
+int zolo_stats_count(void) {
+    zolo::Registry& r = zolo::reg();
+    std::lock_guard<std::mutex> lock(r.mu);
+    return (int)r.entries.size();
+}
 
 int zolo_stats_get(int index, char* name, int name_len, long long* launches, double* ms, double* flops,
                    double* bytes) {
     zolo::Registry& r = zolo::reg();
+    std::lock_guard<std::mutex> lock(r.mu);
     r.collect();
     if (index < 0 || index >= (int)r.entries.size()) return -1;
     const zolo::Entry& e = r.entries[index];

@@ -23,11 +23,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "../../include/zolo.h"
@@ -105,6 +107,7 @@ Work layout(char* base, int m, int n, int rmax, int panel_coresident, bool mixed
     w.qr.Tb = ar.take<double>(qr_tb_elems(n, rmax));
     w.qr.splitk = ar.take<double>(kQrSplitElems);
     w.qr.splitk_elems = kQrSplitElems;
+    w.qr.panel_stream = nullptr;
     w.qr.Rd = ar.take<double>((size_t)rmax * npanels * kPanelNB * kPanelNB);
     w.qr.S = ar.take<double>((size_t)rmax * kPanelNB * kPanelNB);
     w.qr.partials = ar.take<double>(std::max(qr_partials_elems(m, n, rmax, panel_coresident),
@@ -403,6 +406,9 @@ int zolo_pd(zolo_handle h, int m, int n, const double* A, int lda, double alpha,
         return rc;
     }
     w = layout(h->arena, m, n, rmax, h->panel_coresident, mixed);
+    w.qr.panel_stream = h->panel_stream;
+    w.qr.ev_ready = h->ev_ready;
+    w.qr.ev_done = h->ev_done;
     hipStream_t st = h->stream;
     int* hi = reinterpret_cast<int*>(h->host);
     // Stage times: drain the stream first so queued work is charged to the
@@ -617,15 +623,80 @@ int zolo_pd_batched(zolo_handle h, int count, const int* m, const int* n, const 
         need = std::max(need, layout(nullptr, m[i], n[i], rmax, h->panel_coresident,
                                      opts && opts->precision == 1).bytes);
     }
-    if (int rc = ensure(h, need)) return rc;
-    int worst = 0;
-    for (int i = 0; i < count; ++i) {
-        const int rc = zolo_pd(h, m[i], n[i], A[i], lda[i], alpha ? alpha[i] : 0.0, l ? l[i] : 0.0, r ? r[i] : 0,
-                               Qp[i], ldq[i], H[i], ldh[i], opts, info ? info + i : nullptr);
-        if (rc < 0 || rc > ZOLO_NOT_CONVERGED) return rc;
-        worst = std::max(worst, rc);
+    const int streams = std::min(count, (opts && opts->batch_streams > 0) ? opts->batch_streams : 4);
+    if (streams <= 1) {
+        if (int rc = ensure(h, need)) return rc;
+        int worst = 0;
+        for (int i = 0; i < count; ++i) {
+            const int rc = zolo_pd(h, m[i], n[i], A[i], lda[i], alpha ? alpha[i] : 0.0, l ? l[i] : 0.0,
+                                   r ? r[i] : 0, Qp[i], ldq[i], H[i], ldh[i], opts, info ? info + i : nullptr);
+            if (rc < 0 || rc > ZOLO_NOT_CONVERGED) return rc;
+            worst = std::max(worst, rc);
+        }
+        return worst;
     }
-    return worst;
+    // Several solves at once: worker handles with their own stream, pinned
+    // read-back buffer and workspace, pulling matrices from a shared counter;
+    // their cooperative panels all go to one shared panel stream.
+    // The inputs may still be in flight on the caller's stream.
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return ZOLO_HIP;
+    hipStream_t panel_stream = nullptr;
+    if (hipStreamCreate(&panel_stream) != hipSuccess) return ZOLO_HIP;
+    std::vector<zolo_handle_s> wk(streams);
+    int setup = 0;
+    for (int t = 0; t < streams && !setup; ++t) {
+        zolo_handle_s& x = wk[t];
+        x.device = h->device;
+        x.panel_coresident = h->panel_coresident;
+        x.est = h->est;
+        x.panel_stream = panel_stream;
+        if (hipStreamCreate(&x.stream) != hipSuccess || hipHostMalloc((void**)&x.host, 4096) != hipSuccess ||
+            hipEventCreateWithFlags(&x.ev_ready, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&x.ev_done, hipEventDisableTiming) != hipSuccess)
+            setup = ZOLO_HIP;
+        else if (ensure(&x, need))
+            setup = ZOLO_ALLOC;
+    }
+    std::atomic<int> next(0), worst(0), failed(0);
+    auto work = [&](zolo_handle_s* x) {
+        if (hipSetDevice(x->device) != hipSuccess) {
+            failed.store(ZOLO_HIP);
+            return;
+        }
+        for (;;) {
+            if (failed.load()) return;
+            const int i = next.fetch_add(1);
+            if (i >= count) return;
+            const int rc = zolo_pd(x, m[i], n[i], A[i], lda[i], alpha ? alpha[i] : 0.0, l ? l[i] : 0.0,
+                                   r ? r[i] : 0, Qp[i], ldq[i], H[i], ldh[i], opts, info ? info + i : nullptr);
+            if (rc < 0 || rc > ZOLO_NOT_CONVERGED) {
+                int expected = 0;
+                failed.compare_exchange_strong(expected, rc);
+                return;
+            }
+            int cur = worst.load();
+            while (rc > cur && !worst.compare_exchange_weak(cur, rc)) {
+            }
+        }
+    };
+    if (!setup) {
+        std::vector<std::thread> threads;
+        for (int t = 0; t < streams; ++t) threads.emplace_back(work, &wk[t]);
+        for (std::thread& th : threads) th.join();
+    }
+    for (zolo_handle_s& x : wk) {
+        if (x.stream) (void)hipStreamSynchronize(x.stream);
+        if (x.arena) (void)hipFree(x.arena);
+        if (x.host) (void)hipHostFree(x.host);
+        if (x.ev_ready) (void)hipEventDestroy(x.ev_ready);
+        if (x.ev_done) (void)hipEventDestroy(x.ev_done);
+        if (x.stream) (void)hipStreamDestroy(x.stream);
+    }
+    (void)hipStreamSynchronize(panel_stream);
+    (void)hipStreamDestroy(panel_stream);
+    if (setup) return setup;
+    if (failed.load()) return failed.load();
+    return worst.load();
 }
 
 }  // extern "C"

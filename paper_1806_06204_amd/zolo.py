@@ -26,7 +26,7 @@ STATUS = {0: "ok", 1: "not converged", 2: "non-finite input", 3: "allocation fai
 class ZoloOpts(ctypes.Structure):
     _fields_ = [("max_iter", c_int), ("stop_rule", c_int), ("tau", c_double), ("chol_switch", c_double),
                 ("qr_variant", c_int), ("precision", c_int), ("compute_errors", c_int), ("l_source", c_int),
-                ("reserved", c_int * 8)]
+                ("batch_streams", c_int), ("reserved", c_int * 7)]
 
 
 class ZoloInfo(ctypes.Structure):
@@ -218,7 +218,7 @@ class Zolo:
         o = ZoloOpts()
         load().zolo_default_opts(ctypes.byref(o))
         names = {"max_iter", "stop_rule", "tau", "chol_switch", "qr_variant", "precision", "compute_errors",
-                 "l_source"}
+                 "l_source", "batch_streams"}
         for k, v in kw.items():
             if k not in names:
                 raise TypeError(f"unknown option {k}")

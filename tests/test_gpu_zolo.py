@@ -242,3 +242,17 @@ def test_overestimated_l_is_reestimated(z, m, n, kappa, l_given, r):
     assert "".join(info["kinds"]) == "".join(io["kinds"])
     assert info["bwd_err"] <= BAR and info["orth_err"] <= BAR
     assert np.linalg.norm(H.cpu().numpy() - Ho) <= 1e-12 * np.linalg.norm(Ho)
+
+
+def test_batched_streams_match_sequential(z):
+    # Concurrent solves (several streams, one shared panel stream) give the
+    # same bits as one solve after another: every kernel is deterministic.
+    specs = W.batch_specs(count=10, seed=4200, nmin=40, nmax=700)
+    mats = [dev(W.svd_matrix(sp["m"], sp["n"], sp["kappa"], sp["seed_u"], sp["seed_v"])[0]) for sp in specs]
+    ls = [1.0 / sp["kappa"] for sp in specs]
+    Qs1, Hs1, i1 = z.pd_batched(mats, alphas=[1.0] * len(mats), ls=ls, batch_streams=1)
+    Qs4, Hs4, i4 = z.pd_batched(mats, alphas=[1.0] * len(mats), ls=ls, batch_streams=4)
+    for a, b, c, d, x, y in zip(Qs1, Qs4, Hs1, Hs4, i1, i4):
+        assert x["status"] == 0 and y["status"] == 0 and x["kinds"] == y["kinds"]
+        assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+        assert np.array_equal(c.cpu().numpy(), d.cpu().numpy())
