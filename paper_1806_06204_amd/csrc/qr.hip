@@ -88,16 +88,26 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
     double Trow[kNB];
 #pragma unroll
     for (int l = 0; l < kNB; ++l) Trow[l] = 0.0;
-    if (tid < kNB) s_coef[tid] = 0.0;
+    if (tid < kNB) {
+        s_coef[tid] = 0.0;
+        s_w[kNB + tid] = 0.0;
+    }
     __syncthreads();
     unsigned* ctr = a.counters + b;
 
     for (int k = 0; k < nb; ++k) {
         // Phase A: reflector k-1 on the columns > k (rows >= k-1), dot products
         // of column k below the pivot with every panel column, pivot row values.
-        double acc[kColsPerWave], prv[kColsPerWave];
+        // The wave index is made scalar so that every per-column condition is
+        // uniform, and the wave's update coefficients are read once per column.
+        const int wv = __builtin_amdgcn_readfirstlane(wave);
+        double acc[kColsPerWave], cq[kColsPerWave];
 #pragma unroll
-        for (int q = 0; q < kColsPerWave; ++q) acc[q] = prv[q] = 0.0;
+        for (int q = 0; q < kColsPerWave; ++q) {
+            const int i = wv + 4 * q;
+            acc[q] = 0.0;
+            cq[q] = (k > 0 && i > k && i < nb) ? s_coef[i] : 0.0;
+        }
         const double ck = k > 0 ? s_coef[k] : 0.0;
         const int lo = max(r0, k > 0 ? k - 1 : 0);
         for (int row = lo + lane; row < r1; row += 64) {
@@ -106,38 +116,55 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
             double val[kColsPerWave];
 #pragma unroll
             for (int q = 0; q < kColsPerWave; ++q) {
-                const int i = min(wave + 4 * q, nb - 1);
+                const int i = min(wv + 4 * q, nb - 1);
                 val[q] = X[rl + i * xld];
             }
             const double vraw = k > 0 ? X[rl + (k - 1) * xld] : 0.0;
             const double xraw = X[rl + k * xld];
             const double vprev = k > 0 ? (row == k - 1 ? 1.0 : vraw) : 0.0;
             const double xk = xraw - ck * vprev;
+            const double xa = row > k ? xk : 0.0;  // column k below the pivot
 #pragma unroll
             for (int q = 0; q < kColsPerWave; ++q) {
-                const int i = wave + 4 * q;
-                if (i > k && k > 0) val[q] -= s_coef[min(i, kNB - 1)] * vprev;
-                if (i == k) val[q] = xk;
-                if (i < nb) {
-                    if (row > k) acc[q] += xk * val[q];
-                    else if (row == k) prv[q] = val[q];
-                }
+                const int i = wv + 4 * q;
+                double v = val[q] - cq[q] * vprev;  // cq = 0 leaves columns <= k as they are
+                if (i == k) v = xk;
+                val[q] = v;
+                acc[q] += xa * v;
+                // The pivot row lives in one lane of one workgroup: it writes
+                // the row's values directly (the slots are zero elsewhere).
+                if (row == k && i < nb) s_w[kNB + i] = v;
             }
 #pragma unroll
             for (int q = 0; q < kColsPerWave; ++q) {
-                const int i = wave + 4 * q;
-                if (i > k && k > 0 && i < nb) X[rl + i * xld] = val[q];
+                const int i = wv + 4 * q;
+                if (k > 0 && i > k && i < nb) X[rl + i * xld] = val[q];
             }
         }
+        {
+            // The 16 column sums of the wave in one transposing butterfly:
+            // at offsets 32, 16, 8, 4 each lane keeps half of its values and
+            // adds the partner's copy of that half (17 shuffles instead of
+            // 16 x 6); then lane l holds value (l >> 2) & 15 summed over the
+            // 16 lanes that differ in bits 2-5, and offsets 2, 1 finish it.
+            double h[kColsPerWave];
 #pragma unroll
-        for (int q = 0; q < kColsPerWave; ++q) {
-            const double sa = wave_sum(acc[q]);
-            const double sp = wave_sum(prv[q]);   // only the lane holding the pivot row is nonzero
-            const int i = wave + 4 * q;
-            if (lane == 0 && i < nb) {
-                s_w[i] = sa;
-                s_w[kNB + i] = sp;
+            for (int q = 0; q < kColsPerWave; ++q) h[q] = acc[q];
+#pragma unroll
+            for (int half = kColsPerWave / 2, off = 32; half >= 1; half /= 2, off /= 2) {
+                const bool upper = (lane & off) != 0;
+#pragma unroll
+                for (int j = 0; j < half; ++j) {
+                    const double keep = upper ? h[j + half] : h[j];
+                    const double send = upper ? h[j] : h[j + half];
+                    h[j] = keep + __shfl_xor(send, off, 64);
+                }
             }
+            double t = h[0];
+            t += __shfl_xor(t, 2, 64);
+            t += __shfl_xor(t, 1, 64);
+            const int i = wv + 4 * ((lane >> 2) & 15);
+            if ((lane & 3) == 0 && i < nb) s_w[i] = t;
         }
         __syncthreads();
 
@@ -244,6 +271,7 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
             const double x = X[rl + k * xld] - ck * vprev;
             X[rl + k * xld] = row == k ? beta : (row > k ? scale * x : x);
         }
+        if (tid < kNB) s_w[kNB + tid] = 0.0;  // pivot-row slots of the next column
         __syncthreads();
     }
     // Save the R diagonal block; make V's top block explicit (1 on the
