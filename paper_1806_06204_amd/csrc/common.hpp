@@ -59,6 +59,11 @@ struct GemmDescT {
     // second kernel sums them in order into C.
     int splitk = 1;
     T* work = nullptr;
+    // Set by the launcher when the work per tile is uneven (triangular
+    // operands, upper-tile outputs): XCD x takes the tiles [xsplit[x],
+    // xsplit[x+1]) of the launch order, ranges cut to equal estimated work.
+    int xbal = 0;
+    int xsplit[9] = {};
 };
 using GemmDesc = GemmDescT<double>;
 using SGemmDesc = GemmDescT<float>;
