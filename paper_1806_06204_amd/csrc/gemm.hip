@@ -369,6 +369,14 @@ hipError_t gemm_dispatch(const GemmDescT<T>& d, hipStream_t s) {
 hipError_t gemm(const GemmDesc& d, hipStream_t s) { return gemm_dispatch(d, s); }
 hipError_t gemm(const SGemmDesc& d, hipStream_t s) { return gemm_dispatch(d, s); }
 
+// Split-K for long-k products with few output tiles (the block-reflector
+// products W = V^T C of the structured QR: 128 x n outputs, k = m + 128).
+// Measured on gfx950 over 136-1008 tiles of 64 x 64 and 64 x 128 at
+// k = 8320, batch 8: one piece per tile leaves the last round of workgroups
+// (2 per CU) partly empty, up to 1.6x the balanced time; four pieces are the
+// fastest or within 3% of it across the whole range (more pieces add the
+// partial-sum traffic, fewer leave the rounds uneven).  Below 256 tiles the
+// pieces are raised to about 1024 workgroups in all.
 hipError_t gemm_split(GemmDesc d, double* work, size_t work_elems, hipStream_t s) {
     d.splitk = 1;
     if (work != nullptr && d.batch2 == 1 && d.k >= 1024 && d.m > 0 && d.n > 0 && d.batch > 0 &&
@@ -376,10 +384,10 @@ hipError_t gemm_split(GemmDesc d, double* work, size_t work_elems, hipStream_t s
         const int t = pick_tile(d);
         const int bm = (t & 2) ? 128 : 64, bn = (t & 1) ? 128 : 64;
         const long long tiles = (long long)((d.m + bm - 1) / bm) * ((d.n + bn - 1) / bn) * (d.reduce ? 1 : d.batch);
-        if (tiles < 512) {
-            long long sk = (512 + tiles - 1) / tiles;             // about two workgroups per CU
-            sk = sk < d.k / 512 ? sk : d.k / 512;                 // at least 512 of k per piece
-            sk = sk < 32 ? sk : 32;
+        if (tiles < 1024) {
+            long long sk = std::max(4LL, (1024 + tiles - 1) / tiles);
+            sk = std::min(sk, (long long)d.k / 512);             // at least 512 of k per piece
+            sk = std::min(sk, 32LL);
             const long long per = (long long)d.m * d.n * (d.reduce ? 1 : d.batch);
             if (sk * per > (long long)work_elems) sk = (long long)work_elems / per;
             if (sk > 1) {

@@ -61,14 +61,14 @@ hipError_t trtri_batched(int n, const T* R, long long ldr, long long sr, T* Rinv
 // --- qr.hip ---------------------------------------------------------------
 constexpr int kPanelNB = 64;
 constexpr int kQrBlock = 2 * kPanelNB;  // two panels share one trailing update
-constexpr size_t kQrSplitElems = (size_t)4 << 20;  // split-K workspace of the QR updates (32 MiB)
+constexpr size_t kQrSplitElems = (size_t)4 << 20;  // smallest split-K workspace of the QR updates (32 MiB)
 
 struct QrWork {
     double* W = nullptr;          // qr_w_elems(n, batch) doubles
     double* W2 = nullptr;         // qr_w_elems(n, batch) doubles
     double* T = nullptr;          // batch * npanels * kPanelNB^2 doubles
     double* Tb = nullptr;         // qr_tb_elems(n, batch) doubles (T of each 128-column block)
-    double* splitk = nullptr;     // kQrSplitElems doubles: split-K partial products
+    double* splitk = nullptr;     // qr_split_elems(n, batch) doubles: split-K partial products
     size_t splitk_elems = 0;
     hipStream_t panel_stream = nullptr;        // non-null: launch panels there (see run_panel)
     hipEvent_t ev_ready = nullptr, ev_done = nullptr;
@@ -81,6 +81,11 @@ struct QrWork {
 };
 
 inline size_t qr_w_elems(int n, int batch) { return (size_t)batch * kQrBlock * n; }
+// Split-K partials: four pieces of the largest block-reflector product.
+inline size_t qr_split_elems(int n, int batch) {
+    const size_t e = 4 * qr_w_elems(n, batch);
+    return e > kQrSplitElems ? e : kQrSplitElems;
+}
 inline size_t qr_tb_elems(int n, int batch) {
     return (size_t)batch * ((n + kQrBlock - 1) / kQrBlock) * kQrBlock * kQrBlock;
 }

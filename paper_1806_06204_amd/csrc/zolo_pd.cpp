@@ -105,8 +105,8 @@ Work layout(char* base, int m, int n, int rmax, int panel_coresident, bool mixed
     w.qr.W2 = ar.take<double>(qr_w_elems(n, rmax));
     w.qr.T = ar.take<double>((size_t)rmax * npanels * kPanelNB * kPanelNB);
     w.qr.Tb = ar.take<double>(qr_tb_elems(n, rmax));
-    w.qr.splitk = ar.take<double>(kQrSplitElems);
-    w.qr.splitk_elems = kQrSplitElems;
+    w.qr.splitk = ar.take<double>(qr_split_elems(n, rmax));
+    w.qr.splitk_elems = qr_split_elems(n, rmax);
     w.qr.panel_stream = nullptr;
     w.qr.Rd = ar.take<double>((size_t)rmax * npanels * kPanelNB * kPanelNB);
     w.qr.S = ar.take<double>((size_t)rmax * kPanelNB * kPanelNB);
