@@ -64,6 +64,9 @@ struct GemmDescT {
     // xsplit[x+1]) of the launch order, ranges cut to equal estimated work.
     int xbal = 0;
     int xsplit[9] = {};
+    // Set by the launcher of a kernel that applies alpha and beta * Cin
+    // itself (split-K pieces then hold scaled partials, piece 0 with Cin).
+    int prescaled = 0;
 };
 using GemmDesc = GemmDescT<double>;
 using SGemmDesc = GemmDescT<float>;

@@ -253,8 +253,11 @@ __global__ void splitk_reduce_kernel(GemmDescT<T> d) {
         if (!ok) continue;
         T s = 0;
         for (int z = 0; z < d.splitk; ++z) s += d.work[((long long)z * nout + ob) * mn + r];
-        T v = (T)d.alpha * s;
-        if (d.Cin && d.beta != 0.0) v += (T)d.beta * d.Cin[ob * d.strideCin + gi + (long long)gj * d.ldcin];
+        T v = s;
+        if (!d.prescaled) {
+            v = (T)d.alpha * s;
+            if (d.Cin && d.beta != 0.0) v += (T)d.beta * d.Cin[ob * d.strideCin + gi + (long long)gj * d.ldcin];
+        }
         d.C[ob * d.strideC + gi + (long long)gj * d.ldc] = v;
     }
 }
@@ -334,16 +337,314 @@ hipError_t launch_bm_bn(const GemmDescT<T>& desc, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Tile shape for a descriptor: bit 1 = 128 rows (else 64), bit 0 = 128 columns.
-// Measured on gfx950 (FP64): 64-row tiles, which run two workgroups per CU,
-// beat 128 x 128 on every shape of the solve: 39.7-40.2 TFLOP/s with
-// 64 x 128 against 34.6-35.0 with 128 x 128 at 8192^3, 35.3 against 32.9 on
-// the 128 x 4096 x 8320 x 8 block-reflector products, and on the short-K
-// trailing updates, which are bound by moving C, 64 x 64 reaches 2.5-2.7 TB/s
-// against 2.0-2.2.  64 x 128 is kept for outputs with at least 128 rows and
-// columns that still give a full wave of tiles, 64 x 64 otherwise.
+// FP64 GEMM on the vector units.  On gfx950 the FP64 FMA pipes outrun the
+// FP64 matrix cores (measured peaks 67 and 36-40 TFLOP/s; 61 TFLOP/s for
+// this kernel's inner loop with operands from LDS), so large FP64 products
+// run here.  128 x 128 tiles, 256 threads, 8 x 8 outputs per thread in
+// registers, operands read from LDS as 16-byte pairs (8 reads per 64 FMAs).
+// Thread (tx, ty) = (tid % 16, tid / 16) owns rows 32 q + 2 tx + {0, 1} and
+// columns 32 q + 2 ty + {0, 1}, q = 0..3, so the 16 lanes of a row group
+// read 256 contiguous bytes.  beta * Cin seeds the accumulators and
+// alpha * alpha_b scales A as it is staged, so results are stored straight
+// from the k-loop (in split-K mode piece 0 carries beta * Cin).  Staging,
+// tile order, structure flags and split-K follow gemm_kernel.
+typedef double dpair __attribute__((ext_vector_type(2)));
+constexpr int kValuBK = 8;   // k-slice: 4 staged values per operand and thread
+
+// acc[i][j] += a[i] b[j] for one k step (a, b as 4 pairs each).
+__device__ inline void fma_8x8(double (&acc)[8][8], const dpair (&a)[4], const dpair (&b)[4]) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const double ai = (i & 1) ? a[i >> 1].y : a[i >> 1].x;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[i][j] = fma(ai, (j & 1) ? b[j >> 1].y : b[j >> 1].x, acc[i][j]);
+    }
+}
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256, 2) void dgemm_valu_kernel(GemmDescT<double> d) {
+    constexpr int BM = 128, BN = 128, BK = kValuBK;
+    constexpr int APT = BM * BK / 256, BPT = BN * BK / 256;
+    __shared__ double As[2][BK][BM + kPad];
+    __shared__ double Bs[2][BK][BN + kPad];
+
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int tiles_m = (d.m + BM - 1) / BM, tiles_n = (d.n + BN - 1) / BN;
+    const int nblocks = tiles_m * tiles_n;
+    int lin;
+    if (d.xbal) {
+        const int x = blockIdx.x % kNumXcd, idx = blockIdx.x / kNumXcd;
+        lin = d.xsplit[x] + idx;
+        if (lin >= d.xsplit[x + 1]) return;
+    } else {
+        lin = xcd_remap(blockIdx.x, nblocks);
+    }
+    const int in_group = kTileGroup * tiles_n;
+    const int first_m = (lin / in_group) * kTileGroup;
+    const int gsize = min(tiles_m - first_m, kTileGroup);
+    const int tm = first_m + (lin % in_group) % gsize;
+    const int tn = (lin % in_group) / gsize;
+    const int row0 = tm * BM, col0 = tn * BN;
+    if ((d.flags & kCUpperTiles) && row0 > col0 + BN - 1) return;
+
+    const unsigned fl = d.flags;
+    int kb = 0, ke = d.k;
+    if (fl & kAUpper) kb = max(kb, row0);
+    if (fl & kBLower) kb = max(kb, col0);
+    if (fl & kALower) ke = min(ke, row0 + BM);
+    if (fl & kBUpper) ke = min(ke, col0 + BN);
+    const int nk = ke > kb ? (ke - kb + BK - 1) / BK : 0;
+    const int nbatch = d.reduce ? d.batch : 1;
+    const int bfirst = d.reduce ? 0 : blockIdx.y;
+    const int ntiles = nk * nbatch;
+    const bool split = d.splitk > 1;
+    const int z2 = split ? 0 : blockIdx.z;
+    const int t_begin = split ? (int)((long long)blockIdx.z * ntiles / d.splitk) : 0;
+    const int t_end = split ? (int)((long long)(blockIdx.z + 1) * ntiles / d.splitk) : ntiles;
+    const int nt = t_end - t_begin;
+
+    const int ob = d.reduce ? 0 : blockIdx.y;
+    double* __restrict__ C = d.C + (long long)ob * d.strideC + (long long)z2 * d.strideC2;
+    const double* Cin = d.Cin ? d.Cin + (long long)ob * d.strideCin + (long long)z2 * d.strideCin2 : nullptr;
+
+    double acc[8][8];
+    if (Cin != nullptr && d.beta != 0.0 && (!split || blockIdx.z == 0)) {
+        const double beta = d.beta;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int gi = row0 + 32 * (i >> 1) + 2 * tx + (i & 1);
+                const int gj = col0 + 32 * (j >> 1) + 2 * ty + (j & 1);
+                const bool ok = gi < d.m && gj < d.n;
+                const double v = Cin[ok ? gi + (long long)gj * d.ldcin : 0];
+                acc[i][j] = ok ? beta * v : 0.0;
+            }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc[i][j] = 0.0;
+    }
+
+    // Staging.  A slice that lies inside the matrices and off the diagonal
+    // of a triangular operand (the common case) loads without masks from
+    // per-thread offsets fixed for the whole k-loop, so the vector units
+    // spend their cycles on FMAs; edge and diagonal slices take the masked
+    // path.  Both decisions are uniform over the workgroup.
+    double ra[APT], rb[BPT];
+    unsigned amask = 0, bmask = 0;
+    double al_cur = 1;
+    bool fast_cur = false;
+    // Thread tid stages elements e = tid + 256 s: their offsets differ by a
+    // uniform step in s (2 k-rows or 32 rows/columns of the tile).
+    const long long ka = TA ? 1 : d.lda, kbs = TB ? d.ldb : 1;   // offset step per k
+    const long long offa0 = TA ? (long long)(row0 + tid / BK) * d.lda + tid % BK
+                               : (row0 + tid % BM) + (long long)(tid / BM) * d.lda;
+    const long long offb0 = TB ? (col0 + tid % BN) + (long long)(tid / BN) * d.ldb
+                               : (long long)(col0 + tid / BK) * d.ldb + tid % BK;
+    const long long sa = TA ? (256 / BK) * d.lda : (256 / BM) * d.lda;
+    const long long sb = TB ? (256 / BN) * d.ldb : (256 / BK) * d.ldb;
+    const bool rows_in = row0 + BM <= d.m, cols_in = col0 + BN <= d.n;
+    auto gload = [&](int t) {
+        const int bi = t / nk;
+        const int k0 = kb + (t - bi * nk) * BK;
+        const int b = bfirst + bi;
+        const double* __restrict__ A = d.A + (long long)b * d.strideA + (long long)z2 * d.strideA2;
+        const double* __restrict__ B = d.B + (long long)b * d.strideB + (long long)z2 * d.strideB2;
+        al_cur = d.alpha * (d.nalpha > 0 ? d.alphas[b] : 1.0);
+        bool fast = rows_in && cols_in && k0 + BK <= ke;
+        if (fl & kAUpper) fast = fast && k0 >= row0 + BM - 1;
+        if (fl & kALower) fast = fast && k0 + BK - 1 <= row0;
+        if (fl & kBUpper) fast = fast && k0 + BK - 1 <= col0;
+        if (fl & kBLower) fast = fast && k0 >= col0 + BN - 1;
+        fast_cur = fast;
+        if (fast) {
+            const double* __restrict__ Ak = A + (long long)k0 * ka + offa0;
+            const double* __restrict__ Bk = B + (long long)k0 * kbs + offb0;
+#pragma unroll
+            for (int s = 0; s < APT; ++s) ra[s] = Ak[s * sa];
+#pragma unroll
+            for (int s = 0; s < BPT; ++s) rb[s] = Bk[s * sb];
+            return;
+        }
+        amask = 0;
+        bmask = 0;
+#pragma unroll
+        for (int s = 0; s < APT; ++s) {
+            const int e = tid + 256 * s;
+            const int i = TA ? e / BK : e % BM;
+            const int kk = TA ? e % BK : e / BM;
+            const int gi = row0 + i, gk = k0 + kk;
+            bool ok = gi < d.m && gk < ke;
+            if (fl & kAUpper) ok = ok && gk >= gi;
+            if (fl & kALower) ok = ok && gk <= gi;
+            const long long off = TA ? gk + (long long)gi * d.lda : gi + (long long)gk * d.lda;
+            ra[s] = A[ok ? off : 0];
+            amask |= ok ? (1u << s) : 0u;
+        }
+#pragma unroll
+        for (int s = 0; s < BPT; ++s) {
+            const int e = tid + 256 * s;
+            const int j = TB ? e % BN : e / BK;
+            const int kk = TB ? e / BN : e % BK;
+            const int gj = col0 + j, gk = k0 + kk;
+            bool ok = gj < d.n && gk < ke;
+            if (fl & kBUpper) ok = ok && gk <= gj;
+            if (fl & kBLower) ok = ok && gk >= gj;
+            const long long off = TB ? gj + (long long)gk * d.ldb : gk + (long long)gj * d.ldb;
+            rb[s] = B[ok ? off : 0];
+            bmask |= ok ? (1u << s) : 0u;
+        }
+    };
+    auto lstore = [&](int buf) {
+        if (fast_cur) {
+#pragma unroll
+            for (int s = 0; s < APT; ++s) {
+                const int e = tid + 256 * s;
+                As[buf][TA ? e % BK : e / BM][TA ? e / BK : e % BM] = ra[s] * al_cur;
+            }
+#pragma unroll
+            for (int s = 0; s < BPT; ++s) {
+                const int e = tid + 256 * s;
+                Bs[buf][TB ? e / BN : e % BK][TB ? e % BN : e / BK] = rb[s];
+            }
+            return;
+        }
+#pragma unroll
+        for (int s = 0; s < APT; ++s) {
+            const int e = tid + 256 * s;
+            const int i = TA ? e / BK : e % BM;
+            const int kk = TA ? e % BK : e / BM;
+            As[buf][kk][i] = (amask >> s) & 1u ? ra[s] * al_cur : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < BPT; ++s) {
+            const int e = tid + 256 * s;
+            const int j = TB ? e % BN : e / BK;
+            const int kk = TB ? e / BN : e % BK;
+            Bs[buf][kk][j] = (bmask >> s) & 1u ? rb[s] : 0.0;
+        }
+    };
+
+    if (nt > 0) {
+        gload(t_begin);
+        lstore(0);
+        __syncthreads();
+        if (nt > 1) gload(t_begin + 1);
+        for (int u = 0; u < nt; ++u) {
+            const int cur = u & 1;
+            // Operands of step k+1 are read into the other register set
+            // while the FMAs of step k run (the loop is kept rolled so that
+            // only two sets are live).
+            const double* Ak = &As[cur][0][2 * tx];
+            const double* Bk = &Bs[cur][0][2 * ty];
+            dpair a0[4], b0[4], a1[4], b1[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                a0[q] = *reinterpret_cast<const dpair*>(Ak + 32 * q);
+                b0[q] = *reinterpret_cast<const dpair*>(Bk + 32 * q);
+            }
+#pragma unroll 1
+            for (int k = 0; k < BK; k += 2) {
+                const int k1 = (k + 1) * (BM + kPad), k2 = ((k + 2) % BK) * (BM + kPad);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    a1[q] = *reinterpret_cast<const dpair*>(Ak + k1 + 32 * q);
+                    b1[q] = *reinterpret_cast<const dpair*>(Bk + k1 + 32 * q);
+                }
+                fma_8x8(acc, a0, b0);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    a0[q] = *reinterpret_cast<const dpair*>(Ak + k2 + 32 * q);
+                    b0[q] = *reinterpret_cast<const dpair*>(Bk + k2 + 32 * q);
+                }
+                fma_8x8(acc, a1, b1);
+            }
+            if (u + 1 < nt) {
+                lstore(cur ^ 1);
+                __syncthreads();
+                if (u + 2 < nt) gload(t_begin + u + 2);
+            }
+        }
+    }
+
+    if (split) {
+        const int nout = d.reduce ? 1 : d.batch;
+        double* __restrict__ Wp = d.work + ((long long)blockIdx.z * nout + ob) * ((long long)d.m * d.n);
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int gi = row0 + 32 * (i >> 1) + 2 * tx + (i & 1);
+                const int gj = col0 + 32 * (j >> 1) + 2 * ty + (j & 1);
+                if (gi < d.m && gj < d.n) Wp[gi + (long long)gj * d.m] = acc[i][j];
+            }
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int gi = row0 + 32 * (i >> 1) + 2 * tx + (i & 1);
+            const int gj = col0 + 32 * (j >> 1) + 2 * ty + (j & 1);
+            bool ok = gi < d.m && gj < d.n;
+            if (fl & kCStoreUpper) ok = ok && gi <= gj;
+            if (fl & kCStoreLower) ok = ok && gi >= gj;
+            if (ok) C[gi + (long long)gj * d.ldc] = acc[i][j];
+        }
+}
+
+hipError_t launch_valu(const GemmDescT<double>& desc, hipStream_t s) {
+    GemmDescT<double> d = desc;
+    d.prescaled = 1;
+    const int gx = balance_xcds<double, 128, 128>(d, (d.m + 127) / 128, (d.n + 127) / 128);
+    dim3 grid(gx, d.reduce ? 1 : d.batch, d.splitk > 1 ? d.splitk : d.batch2);
+    char name[64];
+    if (stats_on()) {
+        snprintf(name, sizeof(name), "dgemm_valu<128,128,%c,%c>", d.transa ? 'T' : 'N', d.transb ? 'T' : 'N');
+    } else {
+        name[0] = 0;
+    }
+    StatScope sc(name, s, gemm_flops(d), gemm_bytes(d));
+    const int which = (d.transa ? 2 : 0) + (d.transb ? 1 : 0);
+    if (which == 0) dgemm_valu_kernel<false, false><<<grid, 256, 0, s>>>(d);
+    else if (which == 1) dgemm_valu_kernel<false, true><<<grid, 256, 0, s>>>(d);
+    else if (which == 2) dgemm_valu_kernel<true, false><<<grid, 256, 0, s>>>(d);
+    else dgemm_valu_kernel<true, true><<<grid, 256, 0, s>>>(d);
+    if (d.splitk > 1) {
+        const long long total = (long long)d.m * d.n * (d.reduce ? 1 : d.batch);
+        long long g = (total + 255) / 256;
+        if (g > 2048) g = 2048;
+        splitk_reduce_kernel<double><<<(int)g, 256, 0, s>>>(d);
+    }
+    sc.end();
+    return hipGetLastError();
+}
+
+// Kernel and tile shape for a descriptor: 0-3 = MFMA gemm_kernel (bit 1 =
+// 128 rows, else 64; bit 0 = 128 columns, else 64), 4 = dgemm_valu_kernel.
+// Measured on gfx950 (FP64): 64-row MFMA tiles, which run two workgroups
+// per CU, beat 128 x 128 MFMA tiles on every shape of the solve (39.7-40.2
+// TFLOP/s with 64 x 128 against 34.6-35.0 at 8192^3; 35.3 against 32.9 on
+// the 128 x 4096 x 8320 x 8 block-reflector products; on the short-K
+// trailing updates 64 x 64 moves 2.5-2.7 TB/s against 2.0-2.2).  The
+// vector-FMA kernel is 10-16% faster again on large products whose A is not
+// transposed (45.8 TFLOP/s at 8192^3, 15.8 against 14.1 on the k = 128
+// trailing updates, 43.4 against 38.7 on the batch-reduced combination) and
+// on short-k products with a transposed A (the k = 64 Cholesky updates:
+// 20.6 against 18.0), but 6% slower on long-k transposed-A products, whose
+// A slices it reads in 64-byte pieces.  It needs at least 512 of its
+// 128 x 128 tiles to fill the chip.
 template <class T>
 int pick_tile(const GemmDescT<T>& d) {
+    if constexpr (sizeof(T) == 8) {
+        if ((!d.transa || d.k <= 128) && d.m >= 256 && d.n >= 256) {
+            const long long t128 =
+                (long long)((d.m + 127) / 128) * ((d.n + 127) / 128) * (d.reduce ? 1 : d.batch) * d.batch2;
+            if (t128 >= 512) return 4;
+        }
+    }
     if (d.k <= 128) return 0;
     const long long t1 = (long long)((d.m + 63) / 64) * ((d.n + 127) / 128) * (d.reduce ? 1 : d.batch) * d.batch2;
     if (d.m >= 128 && d.n >= 128 && t1 >= 256) return 1;
@@ -356,7 +657,11 @@ hipError_t gemm_dispatch(const GemmDescT<T>& d, hipStream_t s) {
     if (d.batch <= 0 || d.batch2 <= 0) return hipSuccess;
     if (d.nalpha > kMaxInlineAlpha || (d.nalpha > 0 && d.nalpha < d.batch)) return hipErrorInvalidValue;
     if (d.splitk > 1 && (d.batch2 != 1 || d.work == nullptr)) return hipErrorInvalidValue;
-    switch (pick_tile(d)) {
+    const int t = pick_tile(d);
+    if constexpr (sizeof(T) == 8) {
+        if (t == 4) return launch_valu(d, s);
+    }
+    switch (t) {
         case 0: return launch_bm_bn<T, 64, 64>(d, s);
         case 1: return launch_bm_bn<T, 64, 128>(d, s);
         case 2: return launch_bm_bn<T, 128, 64>(d, s);
@@ -382,7 +687,7 @@ hipError_t gemm_split(GemmDesc d, double* work, size_t work_elems, hipStream_t s
     if (work != nullptr && d.batch2 == 1 && d.k >= 1024 && d.m > 0 && d.n > 0 && d.batch > 0 &&
         !(d.flags & kCUpperTiles)) {
         const int t = pick_tile(d);
-        const int bm = (t & 2) ? 128 : 64, bn = (t & 1) ? 128 : 64;
+        const int bm = (t & 2) || t == 4 ? 128 : 64, bn = (t & 1) || t == 4 ? 128 : 64;
         const long long tiles = (long long)((d.m + bm - 1) / bm) * ((d.n + bn - 1) / bn) * (d.reduce ? 1 : d.batch);
         if (tiles < 1024) {
             long long sk = std::max(4LL, (1024 + tiles - 1) / tiles);

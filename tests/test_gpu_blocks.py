@@ -58,6 +58,31 @@ def test_gemm_large(z):
     assert np.abs(out - A @ B).max() <= 1e-12 * 777
 
 
+@pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_gemm_vector_kernel_shapes(z, ta, tb):
+    # Large enough for the vector-FMA kernel (128 x 128 tiles) where its
+    # rule takes it: ragged in m, n and k, batch 8, alpha and beta.
+    rng = np.random.default_rng(40 + 2 * ta + tb)
+    m, n, k, batch = 1000, 1100, 120 if ta else 300, 8
+    A = rng.standard_normal((batch, k, m) if ta else (batch, m, k))
+    B = rng.standard_normal((batch, n, k) if tb else (batch, k, n))
+    C = rng.standard_normal((batch, m, n))
+    out = z.gemm(dev(A), dev(B), dev(C), transa=ta, transb=tb, alpha=-0.6, beta=1.7).cpu().numpy()
+    opA = np.swapaxes(A, 1, 2) if ta else A
+    opB = np.swapaxes(B, 1, 2) if tb else B
+    ref = -0.6 * opA @ opB + 1.7 * C
+    assert np.abs(out - ref).max() <= 1e-13 * (k + 1) * 4
+
+
+def test_gemm_vector_kernel_layout_identity(z):
+    # Exact permutation products pin the 8 x 8 per-thread output layout.
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((8, 1030, 1024))
+    P = np.stack([np.eye(1024)[rng.permutation(1024)] for _ in range(8)])
+    out = z.gemm(dev(A), dev(P)).cpu().numpy()
+    assert np.array_equal(out, A @ P)
+
+
 # --- FP32 building blocks (the FP32 steps of the mixed schedule) ----------
 # References are FP64 products of the same FP32 inputs; the bound is the
 # usual k u |A||B| with u = 2^-24, taken elementwise.
