@@ -20,6 +20,7 @@
 #include "stats.hpp"
 
 #include <algorithm>
+#include <type_traits>
 #include <cstdio>
 
 namespace zolo {
@@ -177,18 +178,30 @@ __global__ __launch_bounds__(256, (BM * BN >= 128 * 128) ? 1 : 2) void gemm_kern
         if (nt > 1) gload(t_begin + 1);
         for (int u = 0; u < nt; ++u) {
             const int cur = u & 1;
+            // Fragments of the next 4-deep step are read into the other
+            // register set while the MFMAs of this one run.
+            T af[2][FM], bf[2][FN];
+            {
+                const int kr = lane >> 4;
+#pragma unroll
+                for (int i = 0; i < FM; ++i) af[0][i] = As[cur][kr][wm + i * 16 + (lane & 15)];
+#pragma unroll
+                for (int j = 0; j < FN; ++j) bf[0][j] = Bs[cur][kr][wn + j * 16 + (lane & 15)];
+            }
 #pragma unroll
             for (int k4 = 0; k4 < BK; k4 += 4) {
-                T af[FM], bf[FN];
-                const int kr = k4 + (lane >> 4);
+                const int p = (k4 >> 2) & 1;
+                if (k4 + 4 < BK) {
+                    const int kr = k4 + 4 + (lane >> 4);
 #pragma unroll
-                for (int i = 0; i < FM; ++i) af[i] = As[cur][kr][wm + i * 16 + (lane & 15)];
+                    for (int i = 0; i < FM; ++i) af[p ^ 1][i] = As[cur][kr][wm + i * 16 + (lane & 15)];
 #pragma unroll
-                for (int j = 0; j < FN; ++j) bf[j] = Bs[cur][kr][wn + j * 16 + (lane & 15)];
+                    for (int j = 0; j < FN; ++j) bf[p ^ 1][j] = Bs[cur][kr][wn + j * 16 + (lane & 15)];
+                }
 #pragma unroll
                 for (int i = 0; i < FM; ++i)
 #pragma unroll
-                    for (int j = 0; j < FN; ++j) acc[i][j] = Mfma<T>::run(af[i], bf[j], acc[i][j]);
+                    for (int j = 0; j < FN; ++j) acc[i][j] = Mfma<T>::run(af[p][i], bf[p][j], acc[i][j]);
             }
             if (u + 1 < nt) {
                 // The other buffer was last read in iteration u-1, before the
@@ -622,33 +635,429 @@ hipError_t launch_valu(const GemmDescT<double>& desc, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Kernel and tile shape for a descriptor: 0-3 = MFMA gemm_kernel (bit 1 =
-// 128 rows, else 64; bit 0 = 128 columns, else 64), 4 = dgemm_valu_kernel.
-// Measured on gfx950 (FP64): 64-row MFMA tiles, which run two workgroups
-// per CU, beat 128 x 128 MFMA tiles on every shape of the solve (39.7-40.2
-// TFLOP/s with 64 x 128 against 34.6-35.0 at 8192^3; 35.3 against 32.9 on
-// the 128 x 4096 x 8320 x 8 block-reflector products; on the short-K
-// trailing updates 64 x 64 moves 2.5-2.7 TB/s against 2.0-2.2).  The
-// vector-FMA kernel is 10-16% faster again on large products whose A is not
-// transposed (45.8 TFLOP/s at 8192^3, 15.8 against 14.1 on the k = 128
-// trailing updates, 43.4 against 38.7 on the batch-reduced combination) and
-// on short-k products with a transposed A (the k = 64 Cholesky updates:
-// 20.6 against 18.0), but 6% slower on long-k transposed-A products, whose
-// A slices it reads in 64-byte pieces.  It needs at least 512 of its
-// 128 x 128 tiles to fill the chip.
-template <class T>
-int pick_tile(const GemmDescT<T>& d) {
-    if constexpr (sizeof(T) == 8) {
-        if ((!d.transa || d.k <= 128) && d.m >= 256 && d.n >= 256) {
-            const long long t128 =
-                (long long)((d.m + 127) / 128) * ((d.n + 127) / 128) * (d.reduce ? 1 : d.batch) * d.batch2;
-            if (t128 >= 512) return 4;
+// ---------------------------------------------------------------------------
+// FP64 MFMA GEMM with operands copied from global memory straight into LDS
+// (global_load_lds_dwordx4).  Staging through registers costs the wave one
+// LDS write per element and a wait on its own loads; measured at 8192^3 the
+// MFMA loop alone runs at 75 TFLOP/s and only 49 with the register-staged
+// LDS writes.  Here each lane's 16-byte load lands in LDS at its lane slot
+// without passing through registers, three LDS stages keep the loads two
+// k-slices ahead, and a slice whose elements need masking (ragged edges,
+// the diagonal block of a triangular operand) or whose source is not
+// 16-byte aligned is staged through registers into the same layout.
+//
+// Layouts of one operand slice (R rows of op(A), or columns of op(B), by
+// BK = 16), in 16-byte chunks of two elements adjacent in memory:
+//   R-layout (memory contiguous along r: A as is, B transposed): chunk
+//     (r/2, k) at k * R/2 + ((r/2) ^ 8 (k & 1));
+//   K-layout (memory contiguous along k: A transposed, B as is): chunk
+//     (r, k/2) at r * 8 + ((k/2) ^ (r & 7)).
+// The XOR terms spread the 16 lanes of an MFMA fragment read over the LDS
+// banks (2-way at most); a DMA instruction of 64 lanes fills 64 consecutive
+// chunks, reading whole 128-byte lines in both layouts.
+template <int R, bool KC>
+struct Lay {
+    static constexpr int kChunks = R * kBK / 2;
+    static constexpr int kPerWave = kChunks / 64 / 4;   // DMA instructions per wave and slice
+    __device__ static void coords(int slot, int& r, int& kk) {
+        if constexpr (!KC) {
+            kk = slot / (R / 2);
+            r = 2 * ((slot % (R / 2)) ^ ((kk & 1) * 8));
+        } else {
+            r = slot / (kBK / 2);
+            kk = 2 * ((slot % (kBK / 2)) ^ (r & 7));
         }
     }
+    __device__ static int offset(int r, int kk) {   // bytes
+        if constexpr (!KC) return ((kk * (R / 2) + ((r >> 1) ^ ((kk & 1) * 8))) << 4) + ((r & 1) << 3);
+        else return ((r * (kBK / 2) + ((kk >> 1) ^ (r & 7))) << 4) + ((kk & 1) << 3);
+    }
+};
+
+// One 16-byte global -> LDS copy per lane: lane l's bytes land at LDS
+// address lds_base + 16 l.  Written out rather than through the builtin so
+// that the compiler, which cannot tell the three LDS stages' copies apart
+// once the masked staging path joins the loop, does not wait for every copy
+// in flight before each LDS read; the kernel waits for exactly the copies
+// of the slice it is about to read (vmcnt) and publishes them with its
+// barrier.  lds_base is wave-uniform.
+__device__ inline void copy_to_lds16(const double* src, unsigned lds_base) {
+    asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
+                 :
+                 : "v"(src), "s"(lds_base)
+                 : "memory", "m0");
+}
+__device__ inline unsigned lds_addr(const void* p) {
+    return (unsigned)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
+}
+
+// PRE: load the Cin tile before the k-loop (short k-ranges, where its
+// latency would not hide behind the loop); otherwise after it.
+template <int BM, int BN, bool TA, bool TB, bool PRE>
+__global__ __launch_bounds__(256, 2) void dgemm_dma_kernel(GemmDescT<double> d) {
+    constexpr int BK = kBK;
+    constexpr int FM = BM / 32, FN = BN / 32;
+    using LA = Lay<BM, TA>;
+    using LB = Lay<BN, !TB>;
+    constexpr int NA = LA::kChunks * 2, NB = LB::kChunks * 2;   // doubles per slice
+    __shared__ __align__(16) double As0[NA], As1[NA], As2[NA];
+    __shared__ __align__(16) double Bs0[NB], Bs1[NB], Bs2[NB];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    const int wm = (wave & 1) * (BM / 2), wn = (wave >> 1) * (BN / 2);
+    const int tiles_m = (d.m + BM - 1) / BM, tiles_n = (d.n + BN - 1) / BN;
+    const int nblocks = tiles_m * tiles_n;
+    int lin;
+    if (d.xbal) {
+        const int x = blockIdx.x % kNumXcd, idx = blockIdx.x / kNumXcd;
+        lin = d.xsplit[x] + idx;
+        if (lin >= d.xsplit[x + 1]) return;
+    } else {
+        lin = xcd_remap(blockIdx.x, nblocks);
+    }
+    const int in_group = kTileGroup * tiles_n;
+    const int first_m = (lin / in_group) * kTileGroup;
+    const int gsize = min(tiles_m - first_m, kTileGroup);
+    const int tm = first_m + (lin % in_group) % gsize;
+    const int tn = (lin % in_group) / gsize;
+    const int row0 = tm * BM, col0 = tn * BN;
+    if ((d.flags & kCUpperTiles) && row0 > col0 + BN - 1) return;
+
+    const unsigned fl = d.flags;
+    int kb = 0, ke = d.k;
+    if (fl & kAUpper) kb = max(kb, row0);
+    if (fl & kBLower) kb = max(kb, col0);
+    if (fl & kALower) ke = min(ke, row0 + BM);
+    if (fl & kBUpper) ke = min(ke, col0 + BN);
+    const int nk = ke > kb ? (ke - kb + BK - 1) / BK : 0;
+    const int nbatch = d.reduce ? d.batch : 1;
+    const int bfirst = d.reduce ? 0 : blockIdx.y;
+    const int ntiles = nk * nbatch;
+    const bool split = d.splitk > 1;
+    const int z2 = split ? 0 : blockIdx.z;
+    const int t_begin = split ? (int)((long long)blockIdx.z * ntiles / d.splitk) : 0;
+    const int t_end = split ? (int)((long long)(blockIdx.z + 1) * ntiles / d.splitk) : ntiles;
+    const int nt = t_end - t_begin;
+
+    d4 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = d4{0, 0, 0, 0};
+
+    const int ob = d.reduce ? 0 : blockIdx.y;
+    double* __restrict__ C = d.C + (long long)ob * d.strideC + (long long)z2 * d.strideC2;
+    const double* Cin = d.Cin ? d.Cin + (long long)ob * d.strideCin + (long long)z2 * d.strideCin2 : nullptr;
+    const double alpha = d.alpha, beta = d.beta;
+    const bool use_cin = !split && Cin != nullptr && d.beta != 0.0;
+    double cin[FM][FN][4];
+    auto load_cin = [&]() __attribute__((always_inline)) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int gi = row0 + wm + i * 16 + Mfma<double>::row(lane, e);
+                    const int gj = col0 + wn + j * 16 + (lane & 15);
+                    const bool ok = gi < d.m && gj < d.n;
+                    cin[i][j][e] = Cin[ok ? gi + (long long)gj * d.ldcin : 0];
+                }
+    };
+    if (PRE && use_cin) load_cin();
+
+    // Rows of op(A) past m and columns of op(B) past n only reach outputs
+    // that are never stored, so the copies of an edge tile read clamped rows
+    // (columns) instead of masking them.  A pair of rows (R-layout) must not
+    // straddle the edge: with an odd extent such tiles take the masked path.
+    const bool a_edge_ok = row0 + BM <= d.m || TA || (d.m & 1) == 0;
+    const bool b_edge_ok = col0 + BN <= d.n || !TB || (d.n & 1) == 0;
+    const int a_last = TA ? d.m - 1 : d.m - 2, b_last = TB ? d.n - 2 : d.n - 1;
+    const bool lda_even = (d.lda & 1) == 0, ldb_even = (d.ldb & 1) == 0;
+
+    // Per-lane element offsets of this wave's DMA chunks, less the k0 term.
+    long long dA[LA::kPerWave], dB[LB::kPerWave];
+#pragma unroll
+    for (int q = 0; q < LA::kPerWave; ++q) {
+        int r, kk;
+        LA::coords((wv * LA::kPerWave + q) * 64 + lane, r, kk);
+        const int gi = max(min(row0 + r, a_last), 0);
+        dA[q] = TA ? kk + (long long)gi * d.lda : gi + (long long)kk * d.lda;
+    }
+#pragma unroll
+    for (int q = 0; q < LB::kPerWave; ++q) {
+        int r, kk;
+        LB::coords((wv * LB::kPerWave + q) * 64 + lane, r, kk);
+        const int gj = max(min(col0 + r, b_last), 0);
+        dB[q] = TB ? gj + (long long)kk * d.ldb : kk + (long long)gj * d.ldb;
+    }
+    const long long ka = TA ? 1 : d.lda, kbs = TB ? d.ldb : 1;   // offset step per k
+
+    // Stage slice t of the (batch, k) sequence into one LDS stage.  Returns
+    // the number of DMA instructions this wave left in flight.
+    auto issue = [&](int t, double* sa, double* sb) __attribute__((always_inline)) -> int {
+        const int bi = t / nk;
+        const int k0 = kb + (t - bi * nk) * BK;
+        const int b = bfirst + bi;
+        const double* __restrict__ A = d.A + (long long)b * d.strideA + (long long)z2 * d.strideA2;
+        const double* __restrict__ B = d.B + (long long)b * d.strideB + (long long)z2 * d.strideB2;
+        bool fast = a_edge_ok && b_edge_ok && k0 + BK <= ke && lda_even && ldb_even &&
+                    ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 15) == 0;
+        if (fl & kAUpper) fast = fast && k0 >= row0 + BM - 1;
+        if (fl & kALower) fast = fast && k0 + BK - 1 <= row0;
+        if (fl & kBUpper) fast = fast && k0 + BK - 1 <= col0;
+        if (fl & kBLower) fast = fast && k0 >= col0 + BN - 1;
+        if (fast) {
+            const double* Ak = A + (long long)k0 * ka;
+            const double* Bk = B + (long long)k0 * kbs;
+            const unsigned la = __builtin_amdgcn_readfirstlane(lds_addr(sa) + wv * LA::kPerWave * 1024);
+            const unsigned lb = __builtin_amdgcn_readfirstlane(lds_addr(sb) + wv * LB::kPerWave * 1024);
+#pragma unroll
+            for (int q = 0; q < LA::kPerWave; ++q) copy_to_lds16(Ak + dA[q], la + q * 1024);
+#pragma unroll
+            for (int q = 0; q < LB::kPerWave; ++q) copy_to_lds16(Bk + dB[q], lb + q * 1024);
+            return LA::kPerWave + LB::kPerWave;
+        }
+        // Masked staging through registers, same chunk layout (rare: its
+        // lane-dependent terms are recomputed here rather than kept live).
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
+#pragma unroll
+        for (int q = 0; q < LA::kPerWave; ++q) {
+            const int ins = wv * LA::kPerWave + q, slot = ins * 64 + ln;
+            int r, kk;
+            LA::coords(slot, r, kk);
+            double v[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int gi = row0 + r + (TA ? 0 : h), gk = k0 + kk + (TA ? h : 0);
+                bool ok = gi < d.m && gk < ke;
+                if (fl & kAUpper) ok = ok && gk >= gi;
+                if (fl & kALower) ok = ok && gk <= gi;
+                const long long off = TA ? gk + (long long)gi * d.lda : gi + (long long)gk * d.lda;
+                const double x = A[ok ? off : 0];
+                v[h] = ok ? x : 0.0;
+            }
+            *reinterpret_cast<dpair*>(sa + 2 * slot) = dpair{v[0], v[1]};
+        }
+#pragma unroll
+        for (int q = 0; q < LB::kPerWave; ++q) {
+            const int ins = wv * LB::kPerWave + q, slot = ins * 64 + ln;
+            int r, kk;
+            LB::coords(slot, r, kk);
+            double v[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int gj = col0 + r + (TB ? h : 0), gk = k0 + kk + (TB ? 0 : h);
+                bool ok = gj < d.n && gk < ke;
+                if (fl & kBUpper) ok = ok && gk <= gj;
+                if (fl & kBLower) ok = ok && gk >= gj;
+                const long long off = TB ? gj + (long long)gk * d.ldb : gk + (long long)gj * d.ldb;
+                const double x = B[ok ? off : 0];
+                v[h] = ok ? x : 0.0;
+            }
+            *reinterpret_cast<dpair*>(sb + 2 * slot) = dpair{v[0], v[1]};
+        }
+        return 0;
+    };
+
+    // Per-lane byte offsets of the MFMA fragments at the first 4-deep step;
+    // later steps add a constant (R-layout: 4 k-rows; K-layout: 2 chunk
+    // columns, with the XOR applied to the low chunk bit only... see offset).
+    const int ra0 = lane & 15, kl = lane >> 4;
+    // SCALE: per-batch multipliers (batch-reduced products with alphas).
+    auto compute_k = [&](const double* sa, const double* sb, int t, auto scale_) __attribute__((always_inline)) {
+        constexpr bool SCALE = decltype(scale_)::value;
+        const char* ca = reinterpret_cast<const char*>(sa);
+        const char* cb = reinterpret_cast<const char*>(sb);
+        double al = 1.0;
+        if (SCALE) al = d.alphas[bfirst + t / nk];
+        double af[2][FM], bf[2][FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) af[0][i] = *reinterpret_cast<const double*>(ca + LA::offset(wm + i * 16 + ra0, kl));
+#pragma unroll
+        for (int j = 0; j < FN; ++j) bf[0][j] = *reinterpret_cast<const double*>(cb + LB::offset(wn + j * 16 + ra0, kl));
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+            const int p = s4 & 1;
+            if (s4 + 1 < 4) {
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+                    af[p ^ 1][i] = *reinterpret_cast<const double*>(ca + LA::offset(wm + i * 16 + ra0, 4 * (s4 + 1) + kl));
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    bf[p ^ 1][j] = *reinterpret_cast<const double*>(cb + LB::offset(wn + j * 16 + ra0, 4 * (s4 + 1) + kl));
+            }
+            if (SCALE) {
+#pragma unroll
+                for (int i = 0; i < FM; ++i) af[p][i] *= al;
+            }
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j) acc[i][j] = mfma_f64_16x16x4(af[p][i], bf[p][j], acc[i][j]);
+        }
+    };
+    const bool scaled = d.nalpha > 0;
+    auto compute = [&](const double* sa, const double* sb, int t) __attribute__((always_inline)) {
+        if (scaled) compute_k(sa, sb, t, std::true_type{});
+        else compute_k(sa, sb, t, std::false_type{});
+    };
+
+    // Three-stage ring, loads two slices ahead.  Before the barrier that
+    // opens slice u each wave waits for its own loads of slice u (those of
+    // slice u+1 may stay in flight); the barrier also ends every read of
+    // the stage that slice u+2 then refills.
+    // The barrier is written out: __syncthreads() would also wait for every
+    // load in flight, including the next slice's.  LDS writes of a masked
+    // slice are waited for (lgkmcnt) before it.
+    auto wait_for = [&](int inflight_next) __attribute__((always_inline)) {
+        if (inflight_next >= 6) __builtin_amdgcn_s_waitcnt(0x0F76);
+        else if (inflight_next == 4) __builtin_amdgcn_s_waitcnt(0x0F74);
+        else __builtin_amdgcn_s_waitcnt(0x0F70);
+    };
+    auto barrier = [&]() __attribute__((always_inline)) {
+        __builtin_amdgcn_s_waitcnt(0xC07F);
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+    };
+    if (nt > 0) {
+        int n0 = issue(t_begin, As0, Bs0);
+        int n1 = nt > 1 ? issue(t_begin + 1, As1, Bs1) : 0;
+        (void)n0;
+        for (int u = 0; u < nt; u += 3) {
+            wait_for(u + 1 < nt ? n1 : 0);
+            barrier();
+            int n2 = u + 2 < nt ? issue(t_begin + u + 2, As2, Bs2) : 0;
+            compute(As0, Bs0, t_begin + u);
+            if (u + 1 >= nt) break;
+            wait_for(u + 2 < nt ? n2 : 0);
+            barrier();
+            int n3 = u + 3 < nt ? issue(t_begin + u + 3, As0, Bs0) : 0;
+            compute(As1, Bs1, t_begin + u + 1);
+            if (u + 2 >= nt) break;
+            wait_for(u + 3 < nt ? n3 : 0);
+            barrier();
+            n1 = u + 4 < nt ? issue(t_begin + u + 4, As1, Bs1) : 0;
+            compute(As2, Bs2, t_begin + u + 2);
+        }
+    }
+
+    if (split) {
+        const int nout = d.reduce ? 1 : d.batch;
+        double* __restrict__ Wp = d.work + ((long long)blockIdx.z * nout + ob) * ((long long)d.m * d.n);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int gi = row0 + wm + i * 16 + Mfma<double>::row(lane, e);
+                    const int gj = col0 + wn + j * 16 + (lane & 15);
+                    if (gi < d.m && gj < d.n) Wp[gi + (long long)gj * d.m] = acc[i][j][e];
+                }
+        return;
+    }
+    // All Cin loads are issued before the first store (Cin and C may alias).
+    if (!PRE && use_cin) load_cin();
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int gi = row0 + wm + i * 16 + Mfma<double>::row(lane, e);
+                const int gj = col0 + wn + j * 16 + (lane & 15);
+                bool ok = gi < d.m && gj < d.n;
+                if (fl & kCStoreUpper) ok = ok && gi <= gj;
+                if (fl & kCStoreLower) ok = ok && gi >= gj;
+                if (ok) {
+                    double v = alpha * acc[i][j][e];
+                    if (use_cin) v += beta * cin[i][j][e];
+                    C[gi + (long long)gj * d.ldc] = v;
+                }
+            }
+}
+
+template <int BM, int BN>
+hipError_t launch_dma(const GemmDescT<double>& desc, hipStream_t s) {
+    GemmDescT<double> d = desc;
+    const int gx = balance_xcds<double, BM, BN>(d, (d.m + BM - 1) / BM, (d.n + BN - 1) / BN);
+    dim3 grid(gx, d.reduce ? 1 : d.batch, d.splitk > 1 ? d.splitk : d.batch2);
+    char name[64];
+    if (stats_on()) {
+        snprintf(name, sizeof(name), "dgemm_dma<%d,%d,%c,%c>", BM, BN, d.transa ? 'T' : 'N', d.transb ? 'T' : 'N');
+    } else {
+        name[0] = 0;
+    }
+    StatScope sc(name, s, gemm_flops(d), gemm_bytes(d));
+    const bool pre = d.k <= 256 && BM * BN <= 64 * 64;
+    const int which = (d.transa ? 2 : 0) + (d.transb ? 1 : 0) + (pre ? 4 : 0);
+    switch (which) {
+        case 0: dgemm_dma_kernel<BM, BN, false, false, false><<<grid, 256, 0, s>>>(d); break;
+        case 1: dgemm_dma_kernel<BM, BN, false, true, false><<<grid, 256, 0, s>>>(d); break;
+        case 2: dgemm_dma_kernel<BM, BN, true, false, false><<<grid, 256, 0, s>>>(d); break;
+        case 3: dgemm_dma_kernel<BM, BN, true, true, false><<<grid, 256, 0, s>>>(d); break;
+        default:
+            if constexpr (BM * BN <= 64 * 64) {
+                if (which == 4) dgemm_dma_kernel<BM, BN, false, false, true><<<grid, 256, 0, s>>>(d);
+                else if (which == 5) dgemm_dma_kernel<BM, BN, false, true, true><<<grid, 256, 0, s>>>(d);
+                else if (which == 6) dgemm_dma_kernel<BM, BN, true, false, true><<<grid, 256, 0, s>>>(d);
+                else dgemm_dma_kernel<BM, BN, true, true, true><<<grid, 256, 0, s>>>(d);
+            }
+            break;
+    }
+    if (d.splitk > 1) {
+        const long long total = (long long)d.m * d.n * (d.reduce ? 1 : d.batch);
+        long long g = (total + 255) / 256;
+        if (g > 2048) g = 2048;
+        splitk_reduce_kernel<double><<<(int)g, 256, 0, s>>>(d);
+    }
+    sc.end();
+    return hipGetLastError();
+}
+
+// Kernel and tile shape for a descriptor: 0/1 = MFMA gemm_kernel with
+// 64 x 64 / 64 x 128 tiles, 4 = dgemm_valu_kernel (128 x 128),
+// 5/6 = dgemm_dma_kernel with 64 x 128 / 64 x 64 tiles.  Measured on gfx950
+// (FP64, TFLOP/s; gemm_kernel / vector / DMA kernel):
+//   8192^3 N,N                          39.7 / 46.0 / 56.9
+//   8192^3 T,N upper tiles (Gram)       37.3 / 35.3 / 52.9
+//   8192^3 x 8 N,T batch-reduced        38.5 / 43.3 / 51.2
+//   128 x 8064 x 8320 x 8 T,N, split 4  18.6 / 18.2 / 25.6
+//   4096^3 x 8 N,N triangular A         35.6 / 35.7 / 46.7
+//   8320 x 8064 x 128 x 8 N,N (k=128)   14.2 / 16.0 / 15.9
+//   7936^2 x 64 x 8 T,N upper (k=64)    18.6 / 20.8 / 18.9
+// 64-row MFMA tiles run two workgroups per CU and beat 128 x 128 MFMA tiles
+// on every shape (35 against 40 at 8192^3).  The DMA kernel stages edge
+// tiles through registers when an extent along which its copies run is odd,
+// which is slower than gemm_kernel on small ragged products.
+template <class T>
+int pick_tile(const GemmDescT<T>& d) {
+    const long long nb = (long long)(d.reduce ? 1 : d.batch) * d.batch2;
+    const long long t1 = (long long)((d.m + 63) / 64) * ((d.n + 127) / 128) * nb;
+    if constexpr (sizeof(T) == 8) {
+        if (d.k <= 128) {
+            if (d.m >= 256 && d.n >= 256) {
+                const long long t128 = (long long)((d.m + 127) / 128) * ((d.n + 127) / 128) * nb;
+                if (t128 >= 512) return 4;
+            }
+            return 0;
+        }
+        const bool even_edges = (d.transa || (d.m & 1) == 0) && (!d.transb || (d.n & 1) == 0);
+        const bool even_ld = (d.lda & 1) == 0 && (d.ldb & 1) == 0;
+        if (even_edges && even_ld) return (d.m >= 128 && d.n >= 128 && t1 >= 256) ? 5 : 6;
+    }
     if (d.k <= 128) return 0;
-    const long long t1 = (long long)((d.m + 63) / 64) * ((d.n + 127) / 128) * (d.reduce ? 1 : d.batch) * d.batch2;
     if (d.m >= 128 && d.n >= 128 && t1 >= 256) return 1;
     return 0;
+}
+
+inline void tile_dims(int t, int& bm, int& bn) {
+    bm = t == 4 ? 128 : 64;
+    bn = (t == 1 || t == 4 || t == 5) ? 128 : 64;
 }
 
 template <class T>
@@ -660,6 +1069,8 @@ hipError_t gemm_dispatch(const GemmDescT<T>& d, hipStream_t s) {
     const int t = pick_tile(d);
     if constexpr (sizeof(T) == 8) {
         if (t == 4) return launch_valu(d, s);
+        if (t == 5) return launch_dma<64, 128>(d, s);
+        if (t == 6) return launch_dma<64, 64>(d, s);
     }
     switch (t) {
         case 0: return launch_bm_bn<T, 64, 64>(d, s);
@@ -686,8 +1097,8 @@ hipError_t gemm_split(GemmDesc d, double* work, size_t work_elems, hipStream_t s
     d.splitk = 1;
     if (work != nullptr && d.batch2 == 1 && d.k >= 1024 && d.m > 0 && d.n > 0 && d.batch > 0 &&
         !(d.flags & kCUpperTiles)) {
-        const int t = pick_tile(d);
-        const int bm = (t & 2) || t == 4 ? 128 : 64, bn = (t & 1) || t == 4 ? 128 : 64;
+        int bm, bn;
+        tile_dims(pick_tile(d), bm, bn);
         const long long tiles = (long long)((d.m + bm - 1) / bm) * ((d.n + bn - 1) / bn) * (d.reduce ? 1 : d.batch);
         if (tiles < 1024) {
             long long sk = std::max(4LL, (1024 + tiles - 1) / tiles);

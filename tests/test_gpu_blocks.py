@@ -74,6 +74,24 @@ def test_gemm_vector_kernel_shapes(z, ta, tb):
     assert np.abs(out - ref).max() <= 1e-13 * (k + 1) * 4
 
 
+@pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
+@pytest.mark.parametrize("m,n,k", [(130, 258, 300), (131, 257, 517), (256, 384, 1000), (64, 64, 129)])
+def test_gemm_lds_copy_kernel_shapes(z, ta, tb, m, n, k):
+    # Long-k products (the LDS-copy kernel where its rule takes them): even
+    # and odd edges (clamped copies / masked staging), k not a multiple of
+    # the 16-deep slice, batch 3, alpha and beta.
+    rng = np.random.default_rng(m + 3 * n + 7 * k + 2 * ta + tb)
+    batch = 3
+    A = rng.standard_normal((batch, k, m) if ta else (batch, m, k))
+    B = rng.standard_normal((batch, n, k) if tb else (batch, k, n))
+    C = rng.standard_normal((batch, m, n))
+    out = z.gemm(dev(A), dev(B), dev(C), transa=ta, transb=tb, alpha=1.3, beta=-0.4).cpu().numpy()
+    opA = np.swapaxes(A, 1, 2) if ta else A
+    opB = np.swapaxes(B, 1, 2) if tb else B
+    ref = 1.3 * opA @ opB - 0.4 * C
+    assert np.abs(out - ref).max() <= 1e-13 * (k + 1) * 4
+
+
 def test_gemm_vector_kernel_layout_identity(z):
     # Exact permutation products pin the 8 x 8 per-thread output layout.
     rng = np.random.default_rng(3)
