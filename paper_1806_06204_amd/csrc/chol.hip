@@ -3,10 +3,13 @@
 // step 4(d)): Z_j = X^T X + c_{2j-1} I = R_j^T R_j for all j at once, then
 // R_j^{-1}.
 //
-// POTRF is right-looking with 64-column blocks: a 64 x 64 diagonal block is
-// factored in LDS by one workgroup per matrix (which also inverts it), the row
-// panel to its right becomes R_kk^{-T} Z_12 (one GEMM), and the trailing matrix
-// takes the symmetric rank-64 update on its upper tiles (one GEMM).
+// POTRF is right-looking with 64-column blocks grouped in bands of 256: a
+// 64 x 64 diagonal block is factored in LDS by one workgroup per matrix
+// (which also inverts it), the row panel to its right becomes R_kk^{-T} Z_12
+// (one GEMM), the rows of the band below the block take its rank-64 update,
+// and once the band is done the matrix below it takes one rank-256 update on
+// its upper tiles.  The trailing matrix is thus read and written once per
+// 256 columns rather than once per 64.
 //
 // TRTRI is recursive and level-batched: all 64 x 64 diagonal blocks are
 // inverted at once, then for block sizes s = 64, 128, 256, ... every pair of
@@ -20,6 +23,7 @@ namespace zolo {
 namespace {
 
 constexpr int kB = 64;
+constexpr int kBand = 256;   // columns whose trailing update is applied at once
 
 // Inverse of the upper-triangular kb x kb matrix S (LDS) into Si (LDS):
 // thread j back-substitutes column j.
@@ -117,30 +121,54 @@ hipError_t potrf_batched(int n, T* Z, long long ldz, long long sz, int batch, in
                          hipStream_t st) {
     hipError_t e = hipMemsetAsync(info_dev, 0, sizeof(int) * batch, st);
     if (e != hipSuccess) return e;
-    for (int k0 = 0; k0 < n; k0 += kB) {
-        const int kb = n - k0 < kB ? n - k0 : kB;
-        StatScope sc(sizeof(T) == 8 ? "potrf_diag_kernel<double>" : "potrf_diag_kernel<float>", st,
-                     batch * (double)kb * kb * kb / 3.0);
-        potrf_diag_kernel<T><<<batch, 256, 0, st>>>(k0, kb, Z, ldz, sz, info_dev, work);
-        sc.end();
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        const int rest = n - k0 - kb;
+    for (int k0 = 0; k0 < n; k0 += kBand) {
+        const int band = n - k0 < kBand ? n - k0 : kBand;
+        for (int j0 = k0; j0 < k0 + band; j0 += kB) {
+            const int kb = k0 + band - j0 < kB ? k0 + band - j0 : kB;
+            StatScope sc(sizeof(T) == 8 ? "potrf_diag_kernel<double>" : "potrf_diag_kernel<float>", st,
+                         batch * (double)kb * kb * kb / 3.0);
+            potrf_diag_kernel<T><<<batch, 256, 0, st>>>(j0, kb, Z, ldz, sz, info_dev, work);
+            sc.end();
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            const int rest = n - j0 - kb;
+            if (rest <= 0) break;
+            T* Z12 = Z + j0 + (long long)(j0 + kb) * ldz;
+            // R12 = R_kk^{-T} Z12 over the whole width, in place (one tile
+            // row covers all kb rows).
+            GemmDescT<T> g;
+            g.m = kb; g.n = rest; g.k = kb; g.transa = 1; g.transb = 0;
+            g.A = work; g.lda = kB; g.strideA = (long long)kB * kB;
+            g.B = Z12; g.ldb = ldz; g.strideB = sz;
+            g.C = Z12; g.ldc = ldz; g.strideC = sz;
+            g.beta = 0.0; g.batch = batch; g.flags = kALower;
+            if ((e = gemm(g, st)) != hipSuccess) return e;
+            // Rows of the band below this block take its rank-kb update now
+            // (the next blocks of the band need them); the matrix below the
+            // band waits for the band's combined update.
+            const int rows = k0 + band - j0 - kb;
+            if (rows > 0) {
+                T* Z22 = Z + (j0 + kb) + (long long)(j0 + kb) * ldz;
+                GemmDescT<T> u;
+                u.m = rows; u.n = rest; u.k = kb; u.transa = 1; u.transb = 0;
+                u.A = Z12; u.lda = ldz; u.strideA = sz;
+                u.B = Z12; u.ldb = ldz; u.strideB = sz;
+                u.Cin = Z22; u.ldcin = ldz; u.strideCin = sz;
+                u.C = Z22; u.ldc = ldz; u.strideC = sz;
+                u.alpha = -1.0; u.beta = 1.0; u.batch = batch;
+                u.flags = kCUpperTiles | kCStoreUpper;
+                if ((e = gemm(u, st)) != hipSuccess) return e;
+            }
+        }
+        // Below the band: Z22 -= P^T P with P = the band's rows of R to the
+        // right of the band (one rank-`band` update instead of band/64).
+        const int rest = n - k0 - band;
         if (rest <= 0) break;
-        T* Z12 = Z + k0 + (long long)(k0 + kb) * ldz;
-        // R12 = R_kk^{-T} Z12, in place (one tile row covers all kb rows).
-        GemmDescT<T> g;
-        g.m = kb; g.n = rest; g.k = kb; g.transa = 1; g.transb = 0;
-        g.A = work; g.lda = kB; g.strideA = (long long)kB * kB;
-        g.B = Z12; g.ldb = ldz; g.strideB = sz;
-        g.C = Z12; g.ldc = ldz; g.strideC = sz;
-        g.beta = 0.0; g.batch = batch; g.flags = kALower;
-        if ((e = gemm(g, st)) != hipSuccess) return e;
-        // Z22 -= R12^T R12 on the upper tiles.
-        T* Z22 = Z + (k0 + kb) + (long long)(k0 + kb) * ldz;
+        T* P = Z + k0 + (long long)(k0 + band) * ldz;
+        T* Z22 = Z + (k0 + band) + (long long)(k0 + band) * ldz;
         GemmDescT<T> s;
-        s.m = rest; s.n = rest; s.k = kb; s.transa = 1; s.transb = 0;
-        s.A = Z12; s.lda = ldz; s.strideA = sz;
-        s.B = Z12; s.ldb = ldz; s.strideB = sz;
+        s.m = rest; s.n = rest; s.k = band; s.transa = 1; s.transb = 0;
+        s.A = P; s.lda = ldz; s.strideA = sz;
+        s.B = P; s.ldb = ldz; s.strideB = sz;
         s.Cin = Z22; s.ldcin = ldz; s.strideCin = sz;
         s.C = Z22; s.ldc = ldz; s.strideC = sz;
         s.alpha = -1.0; s.beta = 1.0; s.batch = batch;
