@@ -156,20 +156,21 @@ int zolo_structured_qr_batched(zolo_handle h, int m, int n, const double* pivots
     const size_t blk = (size_t)batch * npanels * kPanelNB * kPanelNB;
     const size_t part = qr_partials_elems(m, e, batch, h->panel_coresident);
     size_t off = 0;
-    const size_t need = 12 * 256 + sizeof(double) * (2 * qr_w_elems(n, batch) + qr_tb_elems(n, batch) + 2 * blk +
-                                                     qr_split_elems(n, batch) +
-                                                     (size_t)batch * kPanelNB * kPanelNB + part) +
+    const size_t need = 14 * 256 + sizeof(double) * (2 * qr_w_elems(n, batch) + qr_tb_elems(n, batch) +
+                                                     qr_ts_elems(n, batch) + 2 * blk + qr_split_elems(n, batch) +
+                                                     qr_s_elems(batch) + part) +
                         sizeof(unsigned) * (size_t)batch * npanels + 64;
     if (int rc = grow(h, need)) return rc;
     QrWork w;
     w.W = (double*)bump(h->arena, off, sizeof(double) * qr_w_elems(n, batch));
     w.W2 = (double*)bump(h->arena, off, sizeof(double) * qr_w_elems(n, batch));
     w.Tb = (double*)bump(h->arena, off, sizeof(double) * qr_tb_elems(n, batch));
+    w.Ts = (double*)bump(h->arena, off, sizeof(double) * qr_ts_elems(n, batch));
     w.splitk = (double*)bump(h->arena, off, sizeof(double) * qr_split_elems(n, batch));
     w.splitk_elems = qr_split_elems(n, batch);
     w.T = (double*)bump(h->arena, off, sizeof(double) * blk);
     w.Rd = (double*)bump(h->arena, off, sizeof(double) * blk);
-    w.S = (double*)bump(h->arena, off, sizeof(double) * (size_t)batch * kPanelNB * kPanelNB);
+    w.S = (double*)bump(h->arena, off, sizeof(double) * qr_s_elems(batch));
     w.partials = (double*)bump(h->arena, off, sizeof(double) * part);
     w.counters = (unsigned*)bump(h->arena, off, sizeof(unsigned) * (size_t)batch * npanels);
     w.error_flag = (int*)bump(h->arena, off, 64);

@@ -60,7 +60,8 @@ hipError_t trtri_batched(int n, const T* R, long long ldr, long long sr, T* Rinv
 
 // --- qr.hip ---------------------------------------------------------------
 constexpr int kPanelNB = 64;
-constexpr int kQrBlock = 2 * kPanelNB;  // two panels share one trailing update
+constexpr int kQrBlock = 2 * kPanelNB;  // two panels: one compact-WY factor Tb
+constexpr int kQrSuper = 2 * kQrBlock;  // two blocks share one trailing update (factor Ts)
 constexpr size_t kQrSplitElems = (size_t)4 << 20;  // smallest split-K workspace of the QR updates (32 MiB)
 
 struct QrWork {
@@ -68,19 +69,24 @@ struct QrWork {
     double* W2 = nullptr;         // qr_w_elems(n, batch) doubles
     double* T = nullptr;          // batch * npanels * kPanelNB^2 doubles
     double* Tb = nullptr;         // qr_tb_elems(n, batch) doubles (T of each 128-column block)
+    double* Ts = nullptr;         // qr_ts_elems(n, batch) doubles (T of each 256-column superblock)
     double* splitk = nullptr;     // qr_split_elems(n, batch) doubles: split-K partial products
     size_t splitk_elems = 0;
     hipStream_t panel_stream = nullptr;        // non-null: launch panels there (see run_panel)
     hipEvent_t ev_ready = nullptr, ev_done = nullptr;
     double* Rd = nullptr;         // batch * npanels * kPanelNB^2 doubles (R diagonal blocks)
-    double* S = nullptr;          // batch * kPanelNB^2 doubles
+    double* S = nullptr;          // qr_s_elems(batch) doubles
     double* partials = nullptr;   // batch * 2 * maxG * 2 * kPanelNB doubles
     unsigned* counters = nullptr; // batch * npanels
     int* error_flag = nullptr;    // 1 int
     int max_coresident = 0;       // workgroups of the panel kernel that fit at once
 };
 
-inline size_t qr_w_elems(int n, int batch) { return (size_t)batch * kQrBlock * n; }
+inline size_t qr_w_elems(int n, int batch) { return (size_t)batch * kQrSuper * n; }
+inline size_t qr_s_elems(int batch) { return (size_t)batch * 2 * kQrBlock * kQrBlock; }
+inline size_t qr_ts_elems(int n, int batch) {
+    return (size_t)batch * ((n + kQrSuper - 1) / kQrSuper) * kQrSuper * kQrSuper;
+}
 // Split-K partials: four pieces of the largest block-reflector product.
 inline size_t qr_split_elems(int n, int batch) {
     const size_t e = 4 * qr_w_elems(n, batch);

@@ -535,114 +535,145 @@ hipError_t apply_block(int L, int c0, int nbv, int trail, const double* Tm, long
     if (trail <= 0) return hipSuccess;
     const double* V = M + c0 + (long long)c0 * ld;
     double* C = M + c0 + (long long)(c0 + nbv) * ld;
-    const long long sw = (long long)kQrBlock * trail;
+    const long long sw = (long long)kQrSuper * trail;
     GemmDesc g1;  // W = V^T C
     g1.m = nbv; g1.n = trail; g1.k = L; g1.transa = 1;
     g1.A = V; g1.lda = ld; g1.strideA = sm;
     g1.B = C; g1.ldb = ld; g1.strideB = sm;
-    g1.C = w.W; g1.ldc = kQrBlock; g1.strideC = sw;
+    g1.C = w.W; g1.ldc = kQrSuper; g1.strideC = sw;
     g1.batch = batch; g1.flags = kAUpper;
     hipError_t err = gemm_split(g1, w.splitk, w.splitk_elems, st);
     if (err != hipSuccess) return err;
     GemmDesc g2;  // W2 = T^T W (forward) or T W (backward)
     g2.m = nbv; g2.n = trail; g2.k = nbv; g2.transa = transpose_t ? 1 : 0;
     g2.A = Tm; g2.lda = ldt; g2.strideA = stt;
-    g2.B = w.W; g2.ldb = kQrBlock; g2.strideB = sw;
-    g2.C = w.W2; g2.ldc = kQrBlock; g2.strideC = sw;
+    g2.B = w.W; g2.ldb = kQrSuper; g2.strideB = sw;
+    g2.C = w.W2; g2.ldc = kQrSuper; g2.strideC = sw;
     g2.batch = batch; g2.flags = transpose_t ? kALower : kAUpper;
     if ((err = gemm(g2, st)) != hipSuccess) return err;
     GemmDesc g3;  // C -= V W2
     g3.m = L; g3.n = trail; g3.k = nbv;
     g3.A = V; g3.lda = ld; g3.strideA = sm;
-    g3.B = w.W2; g3.ldb = kQrBlock; g3.strideB = sw;
+    g3.B = w.W2; g3.ldb = kQrSuper; g3.strideB = sw;
     g3.Cin = C; g3.ldcin = ld; g3.strideCin = sm;
     g3.C = C; g3.ldc = ld; g3.strideC = sm;
     g3.alpha = -1.0; g3.beta = 1.0; g3.batch = batch; g3.flags = kALower;
     return gemm(g3, st);
 }
 
-// Tb = [T1, -T1 (V1^T V2) T2; 0, T2] for the block of panels p, p+1 at
-// column p0 (second panel nb2 wide): the compact-WY factor of the product of
-// the two block reflectors.
-__global__ void assemble_tb_kernel(int nb2, const double* __restrict__ T, long long stT, int p,
-                                   double* __restrict__ Tb, long long stb) {
-    const int b = blockIdx.y;
-    const double* T1 = T + b * stT + (long long)p * kNB * kNB;
-    const double* T2 = T1 + kNB * kNB;
-    double* D = Tb + b * stb;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < kQrBlock * kQrBlock; e += gridDim.x * blockDim.x) {
-        const int i = e % kQrBlock, j = e / kQrBlock;
+// To = [T1, -T1 (V1^T V2) T2; 0, T2]: the compact-WY factor of the product
+// of the block reflectors of columns [c1, c1 + n1) (factor T1) and
+// [c2, c2 + n2), c2 = c1 + n1 (factor T2).  The T12 block is written by the
+// GEMMs before this kernel; the rest is copied or zeroed here.
+__global__ void assemble_wy_kernel(int n1, int n2, const double* __restrict__ T1, long long ld1, long long st1,
+                                   const double* __restrict__ T2, long long ld2, long long st2,
+                                   double* __restrict__ To, long long ldo, long long sto) {
+    const int b = blockIdx.y, nt = n1 + n2;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nt * nt; e += gridDim.x * blockDim.x) {
+        const int i = e % nt, j = e / nt;
+        if (i < n1 && j >= n1) continue;  // T12
         double v = 0.0;
-        if (i < kNB && j < kNB) v = T1[i + j * kNB];
-        else if (i >= kNB && j >= kNB && i < kNB + nb2 && j < kNB + nb2) v = T2[(i - kNB) + (j - kNB) * kNB];
-        else if (i < kNB && j >= kNB && j < kNB + nb2) v = D[e];  // T12, written by the GEMM before this kernel
-        D[e] = v;
+        if (i < n1 && j < n1) v = T1[b * st1 + i + (long long)j * ld1];
+        else if (i >= n1 && j >= n1) v = T2[b * st2 + (i - n1) + (long long)(j - n1) * ld2];
+        To[b * sto + i + (long long)j * ldo] = v;
     }
 }
 
-hipError_t merge_t(int m, int e, int p, int nb2, double* M, long long ld, long long sm, int batch, const QrWork& w,
-                   long long stT, double* Tb, long long stb, hipStream_t st) {
-    const int p0 = p * kNB;
-    const int k = live_rows(m, e, p0, kNB) - kNB;  // rows V1 and V2 share
-    GemmDesc g;  // P = V1^T V2 (64 x nb2) into S
-    g.m = kNB; g.n = nb2; g.k = k; g.transa = 1;
-    g.A = M + (p0 + kNB) + (long long)p0 * ld; g.lda = ld; g.strideA = sm;
-    g.B = M + (p0 + kNB) + (long long)(p0 + kNB) * ld; g.ldb = ld; g.strideB = sm;
-    g.C = w.S; g.ldc = kNB; g.strideC = (long long)kNB * kNB;
-    g.batch = batch;
+hipError_t merge_wy(int m, int e, int c1, int n1, const double* T1, long long ld1, long long st1, int n2,
+                    const double* T2, long long ld2, long long st2, double* M, long long ld, long long sm, int batch,
+                    const QrWork& w, double* To, long long ldo, long long sto, hipStream_t st) {
+    const int c2 = c1 + n1;
+    const int k = live_rows(m, e, c1, n1) - n1;  // rows [c2, end of V1's live rows): V1 is zero below
+    const long long ss = (long long)kQrBlock * kQrBlock;
+    double* P = w.S;
+    double* Y = w.S + (long long)batch * ss;
+    GemmDesc g;  // P = V1^T V2 (n1 x n2); V2's part above its diagonal (zeros, or R of an
+                 // earlier panel of its block) is masked
+    g.m = n1; g.n = n2; g.k = k; g.transa = 1;
+    g.A = M + c2 + (long long)c1 * ld; g.lda = ld; g.strideA = sm;
+    g.B = M + c2 + (long long)c2 * ld; g.ldb = ld; g.strideB = sm;
+    g.C = P; g.ldc = kQrBlock; g.strideC = ss;
+    g.batch = batch; g.flags = kBLower;
     hipError_t err = gemm_split(g, w.splitk, w.splitk_elems, st);
     if (err != hipSuccess) return err;
-    GemmDesc y;  // Y = P T2 into W2 (T2 upper)
-    y.m = kNB; y.n = nb2; y.k = nb2;
-    y.A = w.S; y.lda = kNB; y.strideA = (long long)kNB * kNB;
-    y.B = w.T + (long long)(p + 1) * kNB * kNB; y.ldb = kNB; y.strideB = stT;
-    y.C = w.W2; y.ldc = kNB; y.strideC = (long long)kNB * kNB;
+    GemmDesc y;  // Y = P T2 (T2 upper)
+    y.m = n1; y.n = n2; y.k = n2;
+    y.A = P; y.lda = kQrBlock; y.strideA = ss;
+    y.B = T2; y.ldb = ld2; y.strideB = st2;
+    y.C = Y; y.ldc = kQrBlock; y.strideC = ss;
     y.batch = batch; y.flags = kBUpper;
     if ((err = gemm(y, st)) != hipSuccess) return err;
-    GemmDesc t;  // T12 = -T1 Y (T1 upper) into Tb[0:64, 64:64+nb2]
-    t.m = kNB; t.n = nb2; t.k = kNB;
-    t.A = w.T + (long long)p * kNB * kNB; t.lda = kNB; t.strideA = stT;
-    t.B = w.W2; t.ldb = kNB; t.strideB = (long long)kNB * kNB;
-    t.C = Tb + (long long)kNB * kQrBlock; t.ldc = kQrBlock; t.strideC = stb;
+    GemmDesc t;  // T12 = -T1 Y (T1 upper) into To[0:n1, n1:n1+n2]
+    t.m = n1; t.n = n2; t.k = n1;
+    t.A = T1; t.lda = ld1; t.strideA = st1;
+    t.B = Y; t.ldb = kQrBlock; t.strideB = ss;
+    t.C = To + (long long)n1 * ldo; t.ldc = ldo; t.strideC = sto;
     t.alpha = -1.0; t.batch = batch; t.flags = kAUpper;
     if ((err = gemm(t, st)) != hipSuccess) return err;
-    assemble_tb_kernel<<<dim3(16, batch), 256, 0, st>>>(nb2, w.T, stT, p, Tb, stb);
+    assemble_wy_kernel<<<dim3(16, batch), 256, 0, st>>>(n1, n2, T1, ld1, st1, T2, ld2, st2, To, ldo, sto);
     return hipGetLastError();
 }
 
 }  // namespace
 
+// Panels of 64 columns, paired into 128-column blocks (factor Tb), paired
+// into 256-column superblocks (factor Ts).  Inside a superblock each block's
+// reflectors update the superblock's remaining columns; the rest of the
+// matrix takes one rank-256 block-reflector update per superblock, so the
+// trailing matrix is read and written once per 256 columns.
 hipError_t structured_geqrf(int m, int e, int n, double* M, long long ld, long long sm, int batch, const QrWork& w,
                             hipStream_t st) {
     if (batch > kMaxInlineAlpha || batch < 1) return hipErrorInvalidValue;
     const int npanels = (n + kNB - 1) / kNB;
     const int nblocks = (n + kQrBlock - 1) / kQrBlock;
+    const int nsuper = (n + kQrSuper - 1) / kQrSuper;
     const long long stT = (long long)npanels * kNB * kNB;
     const long long stb = (long long)nblocks * kQrBlock * kQrBlock;
+    const long long sts = (long long)nsuper * kQrSuper * kQrSuper;
     hipError_t err = hipMemsetAsync(w.counters, 0, sizeof(unsigned) * (size_t)batch * npanels, st);
     if (err != hipSuccess) return err;
-    for (int q = 0; q < nblocks; ++q) {
-        const int p0 = q * kQrBlock, p = 2 * q;
-        const int nbq = n - p0 < kQrBlock ? n - p0 : kQrBlock;
-        const int nb1 = nbq < kNB ? nbq : kNB, nb2 = nbq - nb1;
-        const double* T1 = w.T + (long long)p * kNB * kNB;
-        // First panel of the block, then its reflectors on the second panel.
-        if ((err = run_panel(m, e, p, nb1, M, ld, sm, batch, w, stT, st)) != hipSuccess) return err;
-        if (nb2 == 0) {
-            err = apply_block(live_rows(m, e, p0, nb1), p0, nb1, n - p0 - nb1, T1, kNB, stT, true, M, ld, sm, batch,
+    for (int Q = 0; Q < nsuper; ++Q) {
+        const int s0 = Q * kQrSuper;
+        const int nsq = n - s0 < kQrSuper ? n - s0 : kQrSuper, send = s0 + nsq;
+        const int trail_s = n - send;
+        for (int q = 2 * Q; q < 2 * Q + 2 && q < nblocks; ++q) {
+            const int p0 = q * kQrBlock, p = 2 * q;
+            const int nbq = n - p0 < kQrBlock ? n - p0 : kQrBlock;
+            const int nb1 = nbq < kNB ? nbq : kNB, nb2 = nbq - nb1;
+            const int trail_in = send - p0 - nbq;  // columns to the right inside the superblock
+            const double* T1 = w.T + (long long)p * kNB * kNB;
+            if ((err = run_panel(m, e, p, nb1, M, ld, sm, batch, w, stT, st)) != hipSuccess) return err;
+            if (nb2 == 0) {
+                err = apply_block(live_rows(m, e, p0, nb1), p0, nb1, trail_in, T1, kNB, stT, true, M, ld, sm, batch,
+                                  w, st);
+                if (err != hipSuccess) return err;
+                continue;
+            }
+            err = apply_block(live_rows(m, e, p0, nb1), p0, nb1, nb2, T1, kNB, stT, true, M, ld, sm, batch, w, st);
+            if (err != hipSuccess) return err;
+            if ((err = run_panel(m, e, p + 1, nb2, M, ld, sm, batch, w, stT, st)) != hipSuccess) return err;
+            if (trail_in <= 0 && trail_s <= 0) continue;  // no later update needs Tb
+            double* Tb = w.Tb + (long long)q * kQrBlock * kQrBlock;
+            err = merge_wy(m, e, p0, kNB, T1, kNB, stT, nb2, T1 + kNB * kNB, kNB, stT, M, ld, sm, batch, w, Tb,
+                           kQrBlock, stb, st);
+            if (err != hipSuccess) return err;
+            err = apply_block(live_rows(m, e, p0, nbq), p0, nbq, trail_in, Tb, kQrBlock, stb, true, M, ld, sm, batch,
                               w, st);
             if (err != hipSuccess) return err;
-            continue;
         }
-        err = apply_block(live_rows(m, e, p0, nb1), p0, nb1, nb2, T1, kNB, stT, true, M, ld, sm, batch, w, st);
+        if (trail_s <= 0) continue;
+        // The superblock (two full blocks when anything follows it) on the rest.
+        const int nB = nsq - kQrBlock;
+        const double* TA = w.Tb + (long long)(2 * Q) * kQrBlock * kQrBlock;
+        const double* TB = nB > kNB ? w.Tb + (long long)(2 * Q + 1) * kQrBlock * kQrBlock
+                                    : w.T + (long long)(4 * Q + 2) * kNB * kNB;
+        const long long ldB = nB > kNB ? kQrBlock : kNB, stB = nB > kNB ? stb : stT;
+        double* Ts = w.Ts + (long long)Q * kQrSuper * kQrSuper;
+        err = merge_wy(m, e, s0, kQrBlock, TA, kQrBlock, stb, nB, TB, ldB, stB, M, ld, sm, batch, w, Ts, kQrSuper, sts,
+                       st);
         if (err != hipSuccess) return err;
-        if ((err = run_panel(m, e, p + 1, nb2, M, ld, sm, batch, w, stT, st)) != hipSuccess) return err;
-        // Both panels on the rest of the matrix as one 128-column block.
-        const int trail = n - p0 - nbq;
-        if (trail <= 0) continue;
-        double* Tb = w.Tb + (long long)q * kQrBlock * kQrBlock;
-        if ((err = merge_t(m, e, p, nb2, M, ld, sm, batch, w, stT, Tb, stb, st)) != hipSuccess) return err;
-        err = apply_block(live_rows(m, e, p0, nbq), p0, nbq, trail, Tb, kQrBlock, stb, true, M, ld, sm, batch, w, st);
+        err = apply_block(live_rows(m, e, s0, nsq), s0, nsq, trail_s, Ts, kQrSuper, sts, true, M, ld, sm, batch, w,
+                          st);
         if (err != hipSuccess) return err;
     }
     return hipSuccess;
@@ -652,54 +683,69 @@ hipError_t structured_orgqr(int m, int e, int n, double* M, long long ld, long l
                             hipStream_t st) {
     const int npanels = (n + kNB - 1) / kNB;
     const int nblocks = (n + kQrBlock - 1) / kQrBlock;
+    const int nsuper = (n + kQrSuper - 1) / kQrSuper;
     const long long stT = (long long)npanels * kNB * kNB;
     const long long stb = (long long)nblocks * kQrBlock * kQrBlock;
+    const long long sts = (long long)nsuper * kQrSuper * kQrSuper;
     hipError_t err;
-    for (int q = nblocks - 1; q >= 0; --q) {
-        const int p0 = q * kQrBlock;
-        const int nbq = n - p0 < kQrBlock ? n - p0 : kQrBlock;
-        const int trail = n - p0 - nbq;
-        // The block's reflectors on the columns already formed to its right.
-        if (trail > 0) {
-            if (nbq > kNB)
-                err = apply_block(live_rows(m, e, p0, nbq), p0, nbq, trail, w.Tb + (long long)q * kQrBlock * kQrBlock,
-                                  kQrBlock, stb, false, M, ld, sm, batch, w, st);
-            else
-                err = apply_block(live_rows(m, e, p0, nbq), p0, nbq, trail, w.T + (long long)(2 * q) * kNB * kNB, kNB,
-                                  stT, false, M, ld, sm, batch, w, st);
+    for (int Q = nsuper - 1; Q >= 0; --Q) {
+        const int s0 = Q * kQrSuper;
+        const int nsq = n - s0 < kQrSuper ? n - s0 : kQrSuper, send = s0 + nsq;
+        // The superblock's reflectors on the columns already formed to its right
+        // (a superblock that is followed by columns holds two full blocks).
+        if (n - send > 0) {
+            err = apply_block(live_rows(m, e, s0, nsq), s0, nsq, n - send, w.Ts + (long long)Q * kQrSuper * kQrSuper,
+                              kQrSuper, sts, false, M, ld, sm, batch, w, st);
             if (err != hipSuccess) return err;
         }
-        // The block's own columns, panel by panel from the last.
-        for (int p = (nbq > kNB ? 2 * q + 1 : 2 * q); p >= 2 * q; --p) {
-            const int pp0 = p * kNB;
-            const int nb = n - pp0 < kNB ? n - pp0 : kNB;
-            const int L = live_rows(m, e, pp0, nb);
-            const double* Tp = w.T + (long long)p * kNB * kNB;
-            double* V = M + pp0 + (long long)pp0 * ld;
-            const int inblock = p0 + nbq - pp0 - nb;
-            if ((err = apply_block(L, pp0, nb, inblock, Tp, kNB, stT, false, M, ld, sm, batch, w, st)) != hipSuccess)
-                return err;
-            // Panel columns: S = T V_top^T, then Q[rows, panel] = -V S (in place:
-            // one tile column covers the nb <= 64 columns), then +I and zeros above.
-            GemmDesc s;
-            s.m = nb; s.n = nb; s.k = nb; s.transb = 1;
-            s.A = Tp; s.lda = kNB; s.strideA = stT;
-            s.B = V; s.ldb = ld; s.strideB = sm;
-            s.C = w.S; s.ldc = kNB; s.strideC = (long long)kNB * kNB;
-            s.batch = batch; s.flags = kAUpper | kBUpper;
-            if ((err = gemm(s, st)) != hipSuccess) return err;
-            GemmDesc qd;
-            qd.m = L; qd.n = nb; qd.k = nb;
-            qd.A = V; qd.lda = ld; qd.strideA = sm;
-            qd.B = w.S; qd.ldb = kNB; qd.strideB = (long long)kNB * kNB;
-            qd.C = V; qd.ldc = ld; qd.strideC = sm;
-            qd.alpha = -1.0; qd.batch = batch;
-            if ((err = gemm(qd, st)) != hipSuccess) return err;
-            const int total = (pp0 + nb) * nb;
-            int grid = (total + 255) / 256;
-            if (grid > 1024) grid = 1024;
-            orgqr_fix_kernel<<<dim3(grid, batch), 256, 0, st>>>(pp0, nb, M, ld, sm);
-            if ((err = hipGetLastError()) != hipSuccess) return err;
+        for (int q = (2 * Q + 1 < nblocks ? 2 * Q + 1 : 2 * Q); q >= 2 * Q; --q) {
+            const int p0 = q * kQrBlock;
+            const int nbq = n - p0 < kQrBlock ? n - p0 : kQrBlock;
+            const int trail = send - p0 - nbq;
+            // The block's reflectors on the superblock's columns to its right.
+            if (trail > 0) {
+                if (nbq > kNB)
+                    err = apply_block(live_rows(m, e, p0, nbq), p0, nbq, trail,
+                                      w.Tb + (long long)q * kQrBlock * kQrBlock, kQrBlock, stb, false, M, ld, sm, batch,
+                                      w, st);
+                else
+                    err = apply_block(live_rows(m, e, p0, nbq), p0, nbq, trail, w.T + (long long)(2 * q) * kNB * kNB,
+                                      kNB, stT, false, M, ld, sm, batch, w, st);
+                if (err != hipSuccess) return err;
+            }
+            // The block's own columns, panel by panel from the last.
+            for (int p = (nbq > kNB ? 2 * q + 1 : 2 * q); p >= 2 * q; --p) {
+                const int pp0 = p * kNB;
+                const int nb = n - pp0 < kNB ? n - pp0 : kNB;
+                const int L = live_rows(m, e, pp0, nb);
+                const double* Tp = w.T + (long long)p * kNB * kNB;
+                double* V = M + pp0 + (long long)pp0 * ld;
+                const int inblock = p0 + nbq - pp0 - nb;
+                if ((err = apply_block(L, pp0, nb, inblock, Tp, kNB, stT, false, M, ld, sm, batch, w, st)) !=
+                    hipSuccess)
+                    return err;
+                // Panel columns: S = T V_top^T, then Q[rows, panel] = -V S (in place:
+                // one tile column covers the nb <= 64 columns), then +I and zeros above.
+                GemmDesc s;
+                s.m = nb; s.n = nb; s.k = nb; s.transb = 1;
+                s.A = Tp; s.lda = kNB; s.strideA = stT;
+                s.B = V; s.ldb = ld; s.strideB = sm;
+                s.C = w.S; s.ldc = kNB; s.strideC = (long long)kNB * kNB;
+                s.batch = batch; s.flags = kAUpper | kBUpper;
+                if ((err = gemm(s, st)) != hipSuccess) return err;
+                GemmDesc qd;
+                qd.m = L; qd.n = nb; qd.k = nb;
+                qd.A = V; qd.lda = ld; qd.strideA = sm;
+                qd.B = w.S; qd.ldb = kNB; qd.strideB = (long long)kNB * kNB;
+                qd.C = V; qd.ldc = ld; qd.strideC = sm;
+                qd.alpha = -1.0; qd.batch = batch;
+                if ((err = gemm(qd, st)) != hipSuccess) return err;
+                const int total = (pp0 + nb) * nb;
+                int grid = (total + 255) / 256;
+                if (grid > 1024) grid = 1024;
+                orgqr_fix_kernel<<<dim3(grid, batch), 256, 0, st>>>(pp0, nb, M, ld, sm);
+                if ((err = hipGetLastError()) != hipSuccess) return err;
+            }
         }
     }
     return hipSuccess;

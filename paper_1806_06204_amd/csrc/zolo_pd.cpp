@@ -105,11 +105,12 @@ Work layout(char* base, int m, int n, int rmax, int panel_coresident, bool mixed
     w.qr.W2 = ar.take<double>(qr_w_elems(n, rmax));
     w.qr.T = ar.take<double>((size_t)rmax * npanels * kPanelNB * kPanelNB);
     w.qr.Tb = ar.take<double>(qr_tb_elems(n, rmax));
+    w.qr.Ts = ar.take<double>(qr_ts_elems(n, rmax));
     w.qr.splitk = ar.take<double>(qr_split_elems(n, rmax));
     w.qr.splitk_elems = qr_split_elems(n, rmax);
     w.qr.panel_stream = nullptr;
     w.qr.Rd = ar.take<double>((size_t)rmax * npanels * kPanelNB * kPanelNB);
-    w.qr.S = ar.take<double>((size_t)rmax * kPanelNB * kPanelNB);
+    w.qr.S = ar.take<double>(qr_s_elems(rmax));
     w.qr.partials = ar.take<double>(std::max(qr_partials_elems(m, n, rmax, panel_coresident),
                                              qr_partials_elems(m, 0, 1, panel_coresident)));
     w.qr.counters = ar.take<unsigned>((size_t)rmax * npanels);
