@@ -78,29 +78,43 @@ hipError_t gemm(const SGemmDesc& d, hipStream_t stream);
 // and a long k-range is split along k into `work` (up to work_elems doubles).
 hipError_t gemm_split(GemmDesc d, double* work, size_t work_elems, hipStream_t stream);
 
-// Rough count of the floating-point operations a descriptor executes
-// (2 m n k per product, halved per triangular operand / upper-tile output).
-template <class T>
-double gemm_flops(const GemmDescT<T>& d) {
-    double f = 2.0 * d.m * (double)d.n * d.k * d.batch * d.batch2;
-    int tri = 0;
-    if (d.flags & (kAUpper | kALower)) ++tri;
-    if (d.flags & (kBUpper | kBLower)) ++tri;
-    if (tri == 1) f *= 0.5;
-    if (tri == 2) f /= 3.0;
-    if (d.flags & kCUpperTiles) f *= 0.5;
-    return f;
+// Nonzeros of a trapezoidal operand with `r` rows (the side that is not k)
+// and depth k: "from diagonal" = zero where k < r-index (upper op(A), lower
+// op(B)), otherwise zero where k > r-index.
+inline double trapezoid_nnz(double r, double k, bool from_diagonal) {
+    if (from_diagonal) {
+        const double s = r < k ? r : k;
+        return s * k - s * (s - 1) / 2;
+    }
+    return r <= k ? r * (r + 1) / 2 : k * (k + 1) / 2 + (r - k) * k;
 }
 
-// Algorithmic memory traffic of a descriptor in bytes: the used parts of A and
-// B once per batch, Cin when beta != 0 and C once per output (triangular
-// operands and upper-tile outputs halved).
+// Floating-point operations a descriptor executes: 2 m n k per product, a
+// triangular or trapezoidal operand counted by its nonzeros (both
+// triangular: one third of the full product, as for square triangles), and
+// half for upper-tile outputs.
+template <class T>
+double gemm_flops(const GemmDescT<T>& d) {
+    const double nb = (double)d.batch * d.batch2, m = d.m, n = d.n, k = d.k;
+    const bool ta = d.flags & (kAUpper | kALower), tb = d.flags & (kBUpper | kBLower);
+    double f;
+    if (ta && tb) f = 2.0 * m * n * k / 3.0;
+    else if (ta) f = 2.0 * n * trapezoid_nnz(m, k, d.flags & kAUpper);
+    else if (tb) f = 2.0 * m * trapezoid_nnz(n, k, d.flags & kBLower);
+    else f = 2.0 * m * n * k;
+    if (d.flags & kCUpperTiles) f *= 0.5;
+    return f * nb;
+}
+
+// Algorithmic memory traffic of a descriptor in bytes: the nonzeros of A and
+// B once per batch, Cin when beta != 0 and C once per output (upper-tile
+// outputs halved).
 template <class T>
 double gemm_bytes(const GemmDescT<T>& d) {
     const double nb = (double)d.batch * d.batch2, nout = (double)(d.reduce ? 1 : d.batch) * d.batch2;
     double a = (double)d.m * d.k, b = (double)d.k * d.n, c = (double)d.m * d.n;
-    if (d.flags & (kAUpper | kALower)) a *= 0.5;
-    if (d.flags & (kBUpper | kBLower)) b *= 0.5;
+    if (d.flags & (kAUpper | kALower)) a = trapezoid_nnz(d.m, d.k, d.flags & kAUpper);
+    if (d.flags & (kBUpper | kBLower)) b = trapezoid_nnz(d.n, d.k, d.flags & kBLower);
     if (d.flags & kCUpperTiles) c *= 0.5;
     const double cin = (d.Cin && d.beta != 0.0) ? c : 0.0;
     return sizeof(T) * (nb * (a + b) + nout * (c + cin));

@@ -1030,6 +1030,10 @@ hipError_t launch_dma(const GemmDescT<double>& desc, hipStream_t s) {
 //   4096^3 x 8 N,N triangular A         35.6 / 35.7 / 46.7
 //   8320 x 8064 x 128 x 8 N,N (k=128)   14.2 / 16.0 / 15.9
 //   7936^2 x 64 x 8 T,N upper (k=64)    18.6 / 20.8 / 18.9
+//   8320 x 7936 x 256 x 8 N,N (k=256)   30.5 / 36.2 / 37.9 (64 x 64 tiles: 40.5)
+// (counting the nonzeros of trapezoidal operands).  Up to k = 256 the DMA
+// kernel runs 64 x 64 tiles, three workgroups per CU, with Cin loaded before
+// the k-loop; beyond, 64 x 128 and 64 x 64 tiles are equally fast at 8192^3.
 // 64-row MFMA tiles run two workgroups per CU and beat 128 x 128 MFMA tiles
 // on every shape (35 against 40 at 8192^3).  The DMA kernel stages edge
 // tiles through registers when an extent along which its copies run is odd,
@@ -1048,7 +1052,7 @@ int pick_tile(const GemmDescT<T>& d) {
         }
         const bool even_edges = (d.transa || (d.m & 1) == 0) && (!d.transb || (d.n & 1) == 0);
         const bool even_ld = (d.lda & 1) == 0 && (d.ldb & 1) == 0;
-        if (even_edges && even_ld) return (d.m >= 128 && d.n >= 128 && t1 >= 256) ? 5 : 6;
+        if (even_edges && even_ld) return (d.k > 256 && d.m >= 128 && d.n >= 128 && t1 >= 256) ? 5 : 6;
     }
     if (d.k <= 128) return 0;
     if (d.m >= 128 && d.n >= 128 && t1 >= 256) return 1;

@@ -26,12 +26,13 @@
 // Trailing update and Q formation are GEMMs on the MFMA kernel over the live
 // rows:  W = V^T C,  W2 = T^T W,  C -= V W2  (ORGQR: T instead of T^T, last
 // to first, then a panel's own columns = [I; 0] - V (T V_top^T)).  Panels
-// come in pairs: the second panel is updated by the first, and the rest of
-// the matrix by both at once with the compact-WY factor of the pair,
-// T = [T1, -T1 V1^T V2 T2; 0, T2], so each trailing element is read and
-// written once per 128 columns (the stored R entries of the first panel that
-// sit above the second panel's diagonal are masked out of V by the GEMM's
-// triangular flags).
+// come in pairs (blocks) and pairs of blocks (superblocks): the second panel
+// is updated by the first, the second block by the first, and the rest of
+// the matrix by all four panels at once with the compact-WY factor of the
+// product, merged pairwise as T = [T1, -T1 V1^T V2 T2; 0, T2], so each
+// trailing element is read and written once per 256 columns (stored R
+// entries that sit above a later panel's diagonal are masked out of V by the
+// GEMM's triangular flags).
 #include "misc.hpp"
 #include "stats.hpp"
 
@@ -64,10 +65,25 @@ struct PanelArgs {
 // The workgroup's slab (rows [r0, r1) of the panel) lives either in LDS
 // (InLds: loaded once, written back at the end) or stays in global memory.
 // Row r of the slab, column j, is X[(r - r0) + j * xld] with X = LDS or P + r0.
+// One level of the transposing butterfly: lanes with bit OFF set keep the
+// upper HALF of their values, the others the lower, each adding its
+// partner's copy of the kept half (compile-time indices keep h in registers).
+template <int HALF, int OFF>
+__device__ inline void butterfly_step(double (&h)[16], int lane) {
+    const bool upper = (lane & OFF) != 0;
+#pragma unroll
+    for (int j = 0; j < HALF; ++j) {
+        const double keep = upper ? h[j + HALF] : h[j];
+        const double send = upper ? h[j] : h[j + HALF];
+        h[j] = keep + __shfl_xor(send, OFF, 64);
+    }
+}
+
 template <bool InLds>
 __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
     extern __shared__ double smem[];
     __shared__ double s_d[kNB], s_pr[kNB], s_coef[kNB], s_z[kNB], s_w[2 * kNB];
+    __shared__ double s_T[kNB * (kNB + 1) / 2];  // upper T packed by columns: T[i][l] at l (l + 1) / 2 + i
     const int g = blockIdx.x % a.G, b = blockIdx.x / a.G;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const long long ld = a.ld;
@@ -83,11 +99,6 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
             X[rl + j * xld] = P[(r0 + rl) + j * ld];
         }
     }
-    // Thread i < kNB keeps row i of T in registers (indexed only by unrolled
-    // loops, so it never leaves the register file).
-    double Trow[kNB];
-#pragma unroll
-    for (int l = 0; l < kNB; ++l) Trow[l] = 0.0;
     if (tid < kNB) {
         s_coef[tid] = 0.0;
         s_w[kNB + tid] = 0.0;
@@ -96,17 +107,19 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
     unsigned* ctr = a.counters + b;
 
     for (int k = 0; k < nb; ++k) {
-        // Phase A: reflector k-1 on the columns > k (rows >= k-1), dot products
-        // of column k below the pivot with every panel column, pivot row values.
-        // The wave index is made scalar so that every per-column condition is
-        // uniform, and the wave's update coefficients are read once per column.
+        // Phase A: reflector k-1 on the columns > k (rows >= k-1) and the dot
+        // products of column k below the pivot with every panel column.  Wave
+        // w owns columns 16 w .. 16 w + 15; its index is made scalar so that
+        // every per-column condition is uniform.
         const int wv = __builtin_amdgcn_readfirstlane(wave);
+        const int cw = wv * kColsPerWave;
         double acc[kColsPerWave], cq[kColsPerWave];
 #pragma unroll
         for (int q = 0; q < kColsPerWave; ++q) {
-            const int i = wv + 4 * q;
+            const int i = cw + q;
+            const double c = s_coef[i];
             acc[q] = 0.0;
-            cq[q] = (k > 0 && i > k && i < nb) ? s_coef[i] : 0.0;
+            cq[q] = (k > 0 && i > k && i < nb) ? c : 0.0;
         }
         const double ck = k > 0 ? s_coef[k] : 0.0;
         const int lo = max(r0, k > 0 ? k - 1 : 0);
@@ -116,7 +129,7 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
             double val[kColsPerWave];
 #pragma unroll
             for (int q = 0; q < kColsPerWave; ++q) {
-                const int i = min(wv + 4 * q, nb - 1);
+                const int i = min(cw + q, nb - 1);
                 val[q] = X[rl + i * xld];
             }
             const double vraw = k > 0 ? X[rl + (k - 1) * xld] : 0.0;
@@ -126,18 +139,15 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
             const double xa = row > k ? xk : 0.0;  // column k below the pivot
 #pragma unroll
             for (int q = 0; q < kColsPerWave; ++q) {
-                const int i = wv + 4 * q;
+                const int i = cw + q;
                 double v = val[q] - cq[q] * vprev;  // cq = 0 leaves columns <= k as they are
                 if (i == k) v = xk;
                 val[q] = v;
                 acc[q] += xa * v;
-                // The pivot row lives in one lane of one workgroup: it writes
-                // the row's values directly (the slots are zero elsewhere).
-                if (row == k && i < nb) s_w[kNB + i] = v;
             }
 #pragma unroll
             for (int q = 0; q < kColsPerWave; ++q) {
-                const int i = wv + 4 * q;
+                const int i = cw + q;
                 if (k > 0 && i > k && i < nb) X[rl + i * xld] = val[q];
             }
         }
@@ -147,26 +157,30 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
             // adds the partner's copy of that half (17 shuffles instead of
             // 16 x 6); then lane l holds value (l >> 2) & 15 summed over the
             // 16 lanes that differ in bits 2-5, and offsets 2, 1 finish it.
+            static_assert(kColsPerWave == 16, "butterfly written for 16 columns per wave");
             double h[kColsPerWave];
 #pragma unroll
             for (int q = 0; q < kColsPerWave; ++q) h[q] = acc[q];
-#pragma unroll
-            for (int half = kColsPerWave / 2, off = 32; half >= 1; half /= 2, off /= 2) {
-                const bool upper = (lane & off) != 0;
-#pragma unroll
-                for (int j = 0; j < half; ++j) {
-                    const double keep = upper ? h[j + half] : h[j];
-                    const double send = upper ? h[j] : h[j + half];
-                    h[j] = keep + __shfl_xor(send, off, 64);
-                }
-            }
+            butterfly_step<8, 32>(h, lane);
+            butterfly_step<4, 16>(h, lane);
+            butterfly_step<2, 8>(h, lane);
+            butterfly_step<1, 4>(h, lane);
             double t = h[0];
             t += __shfl_xor(t, 2, 64);
             t += __shfl_xor(t, 1, 64);
-            const int i = wv + 4 * ((lane >> 2) & 15);
+            const int i = cw + ((lane >> 2) & 15);
             if ((lane & 3) == 0 && i < nb) s_w[i] = t;
         }
         __syncthreads();
+        // The pivot row after the update, read back by the workgroup that owns
+        // it (its slots stay zero elsewhere): columns > k were stored above,
+        // columns < k are unchanged and column k is recomputed.
+        if (k >= r0 && k < r1 && tid < nb) {
+            const int rl = k - r0;
+            double v = X[rl + tid * xld];
+            if (tid == k) v -= ck * (k > 0 ? X[rl + (k - 1) * xld] : 0.0);
+            s_w[kNB + tid] = v;
+        }
 
         // Phase B: publish, wait for the other slabs of this matrix, sum in order.
         // Partials, counter and polls are device-coherent (agent-scope) atomics.
@@ -209,19 +223,21 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
                 // and add in a fixed order.
                 const int idx = tid < nb ? tid : kNB + (tid - nb);
                 const double* pb = a.partials + ((long long)b * 2 + (k & 1)) * a.G * (2 * kNB);
+                // Sixteen loads in flight per round (clamped index, padded with
+                // +0.0, which leaves the in-order sum unchanged).
                 double sum = 0.0;
-                int gg = 0;
-                for (; gg + 8 <= a.G; gg += 8) {
-                    double v[8];
-    #pragma unroll
-                    for (int u = 0; u < 8; ++u)
-                        v[u] = __hip_atomic_load(&pb[(gg + u) * (2 * kNB) + idx], __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-    #pragma unroll
-                    for (int u = 0; u < 8; ++u) sum += v[u];
+                for (int gg = 0; gg < a.G; gg += 16) {
+                    double v[16];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) {
+                        const int gi = min(gg + u, a.G - 1);
+                        const double x = __hip_atomic_load(&pb[gi * (2 * kNB) + idx], __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+                        v[u] = gg + u < a.G ? x : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) sum += v[u];
                 }
-                for (; gg < a.G; ++gg)
-                    sum += __hip_atomic_load(&pb[gg * (2 * kNB) + idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (tid < nb) s_d[tid] = sum;
                 else s_pr[tid - nb] = sum;
             }
@@ -249,20 +265,16 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
             if (tid < k) s_z[tid] = w;
         }
         __syncthreads();
-        // T[0:k, k] = -tau T[0:k, 0:k] z;  T[k][k] = tau.
-        if (tid < k) {
-            double sum = 0.0;
-#pragma unroll
-            for (int l = 0; l < kNB; ++l)
-                if (l >= tid && l < k) sum += Trow[l] * s_z[l];
-            const double tv = -tau * sum;
-#pragma unroll
-            for (int l = 0; l < kNB; ++l)
-                if (l == k) Trow[l] = tv;
-        } else if (tid == k) {
-#pragma unroll
-            for (int l = 0; l < kNB; ++l)
-                if (l == k) Trow[l] = tau;
+        // T[0:k, k] = -tau T[0:k, 0:k] z;  T[k][k] = tau (T is kept by the
+        // first workgroup of each matrix only).
+        if (g == 0) {
+            if (tid < k) {
+                double sum = 0.0;
+                for (int l = tid; l < k; ++l) sum += s_T[l * (l + 1) / 2 + tid] * s_z[l];
+                s_T[k * (k + 1) / 2 + tid] = -tau * sum;
+            } else if (tid == k) {
+                s_T[k * (k + 1) / 2 + k] = tau;
+            }
         }
         // Phase D: column k: R entry on row k-1, beta on the pivot, v below.
         for (int row = max(r0, k > 0 ? k - 1 : 0) + tid; row < r1; row += kPT) {
@@ -295,8 +307,7 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
     }
     if (g == 0 && tid < kNB) {
         double* Tb = a.T + b * a.st;
-#pragma unroll
-        for (int l = 0; l < kNB; ++l) Tb[tid + l * kNB] = Trow[l];
+        for (int l = 0; l < kNB; ++l) Tb[tid + l * kNB] = (tid <= l && l < nb) ? s_T[l * (l + 1) / 2 + tid] : 0.0;
     }
 }
 
@@ -363,7 +374,7 @@ int panel_rows_target() {
     return v;
 }
 
-constexpr int kStaticLds = 6 * kNB * 8 + 256;
+constexpr int kStaticLds = (6 * kNB + kNB * (kNB + 1) / 2) * 8 + 256;
 
 int lds_limit() {
     static int v = [] {
