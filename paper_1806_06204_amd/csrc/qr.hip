@@ -206,10 +206,13 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
             }
             __syncthreads();
             if (tid == 0) {
-                __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                // The last workgroup to arrive learns it from the counter's old
+                // value and does not poll.
                 const unsigned target = (unsigned)(k + 1) * (unsigned)a.G;
+                const unsigned before = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 unsigned spins = 0;
-                while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                while (before + 1 < target &&
+                       __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
                     if (++spins > a.spin_limit) {
                         atomicOr(a.error_flag, 1);
                         break;
@@ -223,20 +226,20 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
                 // and add in a fixed order.
                 const int idx = tid < nb ? tid : kNB + (tid - nb);
                 const double* pb = a.partials + ((long long)b * 2 + (k & 1)) * a.G * (2 * kNB);
-                // Sixteen loads in flight per round (clamped index, padded with
-                // +0.0, which leaves the in-order sum unchanged).
+                // Thirty-two loads in flight per round (clamped index, padded
+                // with +0.0, which leaves the in-order sum unchanged).
                 double sum = 0.0;
-                for (int gg = 0; gg < a.G; gg += 16) {
-                    double v[16];
+                for (int gg = 0; gg < a.G; gg += 32) {
+                    double v[32];
 #pragma unroll
-                    for (int u = 0; u < 16; ++u) {
+                    for (int u = 0; u < 32; ++u) {
                         const int gi = min(gg + u, a.G - 1);
                         const double x = __hip_atomic_load(&pb[gi * (2 * kNB) + idx], __ATOMIC_RELAXED,
                                                            __HIP_MEMORY_SCOPE_AGENT);
                         v[u] = gg + u < a.G ? x : 0.0;
                     }
 #pragma unroll
-                    for (int u = 0; u < 16; ++u) sum += v[u];
+                    for (int u = 0; u < 32; ++u) sum += v[u];
                 }
                 if (tid < nb) s_d[tid] = sum;
                 else s_pr[tid - nb] = sum;
@@ -269,9 +272,17 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
         // first workgroup of each matrix only).
         if (g == 0) {
             if (tid < k) {
-                double sum = 0.0;
-                for (int l = tid; l < k; ++l) sum += s_T[l * (l + 1) / 2 + tid] * s_z[l];
-                s_T[k * (k + 1) / 2 + tid] = -tau * sum;
+                // Four partial sums break the dependent chain of LDS reads.
+                double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+                int l = tid;
+                for (; l + 3 < k; l += 4) {
+                    s0 += s_T[l * (l + 1) / 2 + tid] * s_z[l];
+                    s1 += s_T[(l + 1) * (l + 2) / 2 + tid] * s_z[l + 1];
+                    s2 += s_T[(l + 2) * (l + 3) / 2 + tid] * s_z[l + 2];
+                    s3 += s_T[(l + 3) * (l + 4) / 2 + tid] * s_z[l + 3];
+                }
+                for (; l < k; ++l) s0 += s_T[l * (l + 1) / 2 + tid] * s_z[l];
+                s_T[k * (k + 1) / 2 + tid] = -tau * ((s0 + s1) + (s2 + s3));
             } else if (tid == k) {
                 s_T[k * (k + 1) / 2 + k] = tau;
             }
