@@ -26,7 +26,8 @@ constexpr int kB = 64;
 constexpr int kBand = 256;   // columns whose trailing update is applied at once
 
 // Inverse of the upper-triangular kb x kb matrix S (LDS) into Si (LDS):
-// thread j back-substitutes column j.
+// thread j back-substitutes column j, Si[i][j] = (delta_ij - sum_k S[i][k]
+// Si[k][j]) / S[i][i] for i = j .. 0, with four partial sums per row.
 template <class T>
 __device__ void lds_upper_inverse(int kb, const T (*S)[kB + 1], T (*Si)[kB + 1]) {
     const int j = threadIdx.x;
@@ -34,9 +35,16 @@ __device__ void lds_upper_inverse(int kb, const T (*S)[kB + 1], T (*Si)[kB + 1])
         for (int i = kB - 1; i > j; --i) Si[i][j] = 0;
         if (j < kb) {
             for (int i = j; i >= 0; --i) {
-                T s = (i == j) ? 1 : 0;
-                for (int k = i + 1; k <= j; ++k) s -= S[i][k] * Si[k][j];
-                Si[i][j] = s / S[i][i];
+                T s0 = (i == j) ? 1 : 0, s1 = 0, s2 = 0, s3 = 0;
+                int k = i + 1;
+                for (; k + 3 <= j; k += 4) {
+                    s0 -= S[i][k] * Si[k][j];
+                    s1 -= S[i][k + 1] * Si[k + 1][j];
+                    s2 -= S[i][k + 2] * Si[k + 2][j];
+                    s3 -= S[i][k + 3] * Si[k + 3][j];
+                }
+                for (; k <= j; ++k) s0 -= S[i][k] * Si[k][j];
+                Si[i][j] = ((s0 + s1) + (s2 + s3)) / S[i][i];
             }
         } else {
             for (int i = 0; i <= j; ++i) Si[i][j] = (i == j) ? 1 : 0;
@@ -44,13 +52,23 @@ __device__ void lds_upper_inverse(int kb, const T (*S)[kB + 1], T (*Si)[kB + 1])
     }
 }
 
+constexpr int kDB = 16;  // column block of the in-LDS factorisation
+
+// Upper Cholesky of the kb x kb diagonal block at (k0, k0) of each matrix
+// (one workgroup per matrix), its inverse into work.  16-column blocks: wave
+// 0 factors the 16 x 16 diagonal block in registers (lane j holds column j,
+// rows broadcast with readlane), one thread per column solves the row panel
+// to its right, and the trailing block takes the rank-16 update, so the
+// factorisation needs 3 barriers per 16 columns.  A non-positive pivot is
+// reported (1-based global column) and replaced by 1 so that every wave
+// finishes; the caller discards the result.
 template <class T>
 __global__ __launch_bounds__(256) void potrf_diag_kernel(int k0, int kb, T* Z, long long ldz, long long sz,
                                                          int* info, T* work) {
     __shared__ T S[kB][kB + 1];
     __shared__ T Si[kB][kB + 1];
     __shared__ int s_bad;
-    const int b = blockIdx.x, tid = threadIdx.x;
+    const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
     T* Zb = Z + b * sz + k0 + (long long)k0 * ldz;
     for (int e = tid; e < kB * kB; e += 256) {
         const int i = e % kB, j = e / kB;
@@ -58,22 +76,67 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(int k0, int kb, T* Z, l
     }
     if (tid == 0) s_bad = 0;
     __syncthreads();
-    for (int k = 0; k < kb; ++k) {
-        if (tid == 0) {
-            T d = S[k][k];
-            if (!(d > (T)0) || !isfinite(d)) {
-                if (s_bad == 0) s_bad = k0 + k + 1;
-                d = 1;  // keep going so every wave finishes; the caller discards the result
+    for (int jb = 0; jb < kb; jb += kDB) {
+        const int bw = kb - jb < kDB ? kb - jb : kDB;
+        if (tid < 64) {
+            // Lane j < 16 holds column jb + j of the diagonal block.
+            T c[kDB];
+#pragma unroll
+            for (int i = 0; i < kDB; ++i) c[i] = (lane < bw && i < bw) ? S[jb + i][jb + (lane & 15)] : (T)0;
+            int bad = 0;
+#pragma unroll
+            for (int i = 0; i < kDB; ++i) {
+                if (i < bw) {
+                    T d = __shfl(c[i], i, 64);
+                    if (!(d > (T)0) || !isfinite(d)) {
+                        if (bad == 0) bad = k0 + jb + i + 1;
+                        d = 1;
+                    }
+                    const T r = sqrt(d), ri = (T)1 / r;
+                    c[i] = lane == i ? r : (lane > i ? c[i] * ri : c[i]);
+#pragma unroll
+                    for (int l = i + 1; l < kDB; ++l) {
+                        const T ril = __shfl(c[i], l, 64);  // R[i][jb + l]
+                        if (lane >= l) c[l] -= ril * c[i];
+                    }
+                }
             }
-            S[k][k] = sqrt(d);
+            if (lane < bw) {
+#pragma unroll
+                for (int i = 0; i < kDB; ++i)
+                    if (i < bw) S[jb + i][jb + lane] = i <= lane ? c[i] : (T)0;
+            }
+            if (lane == 0 && bad != 0 && s_bad == 0) s_bad = bad;
         }
         __syncthreads();
-        if (tid > k && tid < kb) S[k][tid] /= S[k][k];
+        const int c0 = jb + bw, w = kb - c0;
+        if (w <= 0) break;
+        // Row panel: R[jb:jb+bw, c] = R_d^{-T} Z[jb:jb+bw, c], one thread per column.
+        if (tid < w) {
+            const int col = c0 + tid;
+            T x[kDB];
+#pragma unroll
+            for (int i = 0; i < kDB; ++i) {
+                if (i < bw) {
+                    T s0 = S[jb + i][col];
+#pragma unroll
+                    for (int k = 0; k < i; ++k) s0 -= S[jb + k][jb + i] * x[k];
+                    x[i] = s0 / S[jb + i][jb + i];
+                    S[jb + i][col] = x[i];
+                }
+            }
+        }
         __syncthreads();
-        const int w = kb - k - 1;
+        // Trailing block (upper part): S[i][j] -= sum_k R[jb+k][i] R[jb+k][j].
         for (int e = tid; e < w * w; e += 256) {
-            const int ii = k + 1 + e % w, jj = k + 1 + e / w;
-            if (ii <= jj) S[ii][jj] -= S[k][ii] * S[k][jj];
+            const int i = c0 + e % w, j = c0 + e / w;
+            if (i <= j) {
+                T acc = 0;
+#pragma unroll
+                for (int k = 0; k < kDB; ++k)
+                    if (k < bw) acc += S[jb + k][i] * S[jb + k][j];
+                S[i][j] -= acc;
+            }
         }
         __syncthreads();
     }

@@ -20,6 +20,8 @@
 #include "stats.hpp"
 
 #include <algorithm>
+#include <mutex>
+#include <unordered_map>
 #include <type_traits>
 #include <cstdio>
 
@@ -283,12 +285,51 @@ __global__ void splitk_reduce_kernel(GemmDescT<T> d) {
 // order is cut into 8 ranges of equal estimated work (k-slices, plus the
 // epilogue), one per XCD; the grid holds 8 x the longest range and the
 // surplus workgroups return at once.  Returns the grid's x extent.
+// The cut depends only on the launch shape, so it is cached (a solve issues
+// the same shapes again in every step).
+struct BalanceKey {
+    int m, n, k, bm, bn, nbatch;
+    unsigned flags;
+    bool cin;
+    bool operator==(const BalanceKey& o) const {
+        return m == o.m && n == o.n && k == o.k && bm == o.bm && bn == o.bn && nbatch == o.nbatch &&
+               flags == o.flags && cin == o.cin;
+    }
+};
+struct BalanceKeyHash {
+    size_t operator()(const BalanceKey& x) const {
+        size_t h = (size_t)x.m * 1000003u ^ (size_t)x.n * 999983u ^ (size_t)x.k * 998244353u;
+        return h ^ ((size_t)x.flags << 40) ^ ((size_t)x.bm << 48) ^ ((size_t)x.bn << 52) ^
+               ((size_t)x.nbatch << 56) ^ (size_t)x.cin;
+    }
+};
+struct BalanceVal {
+    int xsplit[9];
+};
+std::mutex g_balance_mu;
+std::unordered_map<BalanceKey, BalanceVal, BalanceKeyHash> g_balance_cache;
+
 template <class T, int BM, int BN>
 int balance_xcds(GemmDescT<T>& d, int tiles_m, int tiles_n) {
     const unsigned fl = d.flags;
     const int ntile = tiles_m * tiles_n;
     d.xbal = 0;
     if (!(fl & (kCUpperTiles | kAUpper | kALower | kBUpper | kBLower)) || ntile < 4 * kNumXcd) return ntile;
+    const BalanceKey key{d.m, d.n, d.k, BM, BN, d.reduce ? d.batch : 1, fl, d.Cin != nullptr && d.beta != 0.0};
+    {
+        std::lock_guard<std::mutex> lock(g_balance_mu);
+        auto it = g_balance_cache.find(key);
+        if (it != g_balance_cache.end()) {
+            int longest = 0;
+            for (int i = 0; i < kNumXcd; ++i) {
+                d.xsplit[i] = it->second.xsplit[i];
+                longest = std::max(longest, it->second.xsplit[i + 1] - it->second.xsplit[i]);
+            }
+            d.xsplit[kNumXcd] = it->second.xsplit[kNumXcd];
+            d.xbal = 1;
+            return kNumXcd * longest;
+        }
+    }
     const long long nbatch = d.reduce ? d.batch : 1;
     const long long c0 = 4 + ((d.Cin && d.beta != 0.0) ? 4 : 0);
     const int in_group = kTileGroup * tiles_n;
@@ -319,6 +360,13 @@ int balance_xcds(GemmDescT<T>& d, int tiles_m, int tiles_n) {
     int longest = 0;
     for (int i = 0; i < kNumXcd; ++i) longest = std::max(longest, d.xsplit[i + 1] - d.xsplit[i]);
     d.xbal = 1;
+    {
+        std::lock_guard<std::mutex> lock(g_balance_mu);
+        if (g_balance_cache.size() > 4096) g_balance_cache.clear();
+        BalanceVal v;
+        for (int i = 0; i <= kNumXcd; ++i) v.xsplit[i] = d.xsplit[i];
+        g_balance_cache[key] = v;
+    }
     return kNumXcd * longest;
 }
 
