@@ -25,34 +25,72 @@ namespace {
 constexpr int kB = 64;
 constexpr int kBand = 256;   // columns whose trailing update is applied at once
 
-// Inverse of the upper-triangular kb x kb matrix S (LDS) into Si (LDS):
-// thread j back-substitutes column j, Si[i][j] = (delta_ij - sum_k S[i][k]
-// Si[k][j]) / S[i][i] for i = j .. 0, with four partial sums per row.
+constexpr int kDB = 16;  // column block of the in-LDS factorisation
+
+// Wave-uniform broadcast of lane l's value (readlane, no LDS round trip).
 template <class T>
-__device__ void lds_upper_inverse(int kb, const T (*S)[kB + 1], T (*Si)[kB + 1]) {
-    const int j = threadIdx.x;
-    if (j < kB) {
-        for (int i = kB - 1; i > j; --i) Si[i][j] = 0;
-        if (j < kb) {
-            for (int i = j; i >= 0; --i) {
-                T s0 = (i == j) ? 1 : 0, s1 = 0, s2 = 0, s3 = 0;
-                int k = i + 1;
-                for (; k + 3 <= j; k += 4) {
-                    s0 -= S[i][k] * Si[k][j];
-                    s1 -= S[i][k + 1] * Si[k + 1][j];
-                    s2 -= S[i][k + 2] * Si[k + 2][j];
-                    s3 -= S[i][k + 3] * Si[k + 3][j];
-                }
-                for (; k <= j; ++k) s0 -= S[i][k] * Si[k][j];
-                Si[i][j] = ((s0 + s1) + (s2 + s3)) / S[i][i];
-            }
-        } else {
-            for (int i = 0; i <= j; ++i) Si[i][j] = (i == j) ? 1 : 0;
-        }
+__device__ inline T lane_bcast(T x, int l) {
+    if constexpr (sizeof(T) == 8) {
+        const long long v = __double_as_longlong(x);
+        const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)v, l);
+        const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(v >> 32), l);
+        return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+    } else {
+        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
     }
 }
 
-constexpr int kDB = 16;  // column block of the in-LDS factorisation
+// Inverse of the upper-triangular 64 x 64 matrix S (LDS; identity beyond the
+// matrix) into Si (LDS), by the workgroup's 256 threads.  The four 16 x 16
+// diagonal blocks are inverted at once (wave w inverts block w: lane j
+// back-substitutes column j in registers); then the off-diagonal blocks at
+// distance d = 1, 2, 3 follow from
+//     Si[I][J] = -Si[I][I] sum_{K=I+1..J} S[I][K] Si[K][J].
+template <class T>
+__device__ void lds_upper_inverse(const T (*S)[kB + 1], T (*Si)[kB + 1]) {
+    __shared__ T Y[3][kDB][kDB + 1];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int o = w * kDB;
+    for (int e = tid; e < kB * kB; e += 256) Si[e % kB][e / kB] = 0;
+    __syncthreads();
+    if (lane < kDB) {
+        const int j = lane;
+        T x[kDB];
+#pragma unroll
+        for (int i = kDB - 1; i >= 0; --i) {
+            T s = (i == j) ? (T)1 : (T)0;
+#pragma unroll
+            for (int k = i + 1; k < kDB; ++k) s -= S[o + i][o + k] * x[k];
+            x[i] = i <= j ? s / S[o + i][o + i] : (T)0;
+        }
+#pragma unroll
+        for (int i = 0; i < kDB; ++i) Si[o + i][o + j] = x[i];
+    }
+    __syncthreads();
+    for (int d = 1; d < 4; ++d) {
+        const int nblk = 4 - d;
+        // Y_I = sum_{K=I+1..I+d} S[I][K] Si[K][I+d]
+        for (int e = tid; e < nblk * kDB * kDB; e += 256) {
+            const int I = e / (kDB * kDB), r = e % kDB, c = (e / kDB) % kDB;
+            const int J = I + d;
+            T acc = 0;
+            for (int k = (I + 1) * kDB; k < (J + 1) * kDB; ++k) acc += S[I * kDB + r][k] * Si[k][J * kDB + c];
+            Y[I][r][c] = acc;
+        }
+        __syncthreads();
+        // Si[I][J] = -Si[I][I] Y_I
+        for (int e = tid; e < nblk * kDB * kDB; e += 256) {
+            const int I = e / (kDB * kDB), r = e % kDB, c = (e / kDB) % kDB;
+            const int J = I + d;
+            T acc = 0;
+#pragma unroll
+            for (int k = 0; k < kDB; ++k) acc += Si[I * kDB + r][I * kDB + k] * Y[I][k][c];
+            Si[I * kDB + r][J * kDB + c] = -acc;
+        }
+        __syncthreads();
+    }
+}
+
 
 // Upper Cholesky of the kb x kb diagonal block at (k0, k0) of each matrix
 // (one workgroup per matrix), its inverse into work.  16-column blocks: wave
@@ -67,6 +105,7 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(int k0, int kb, T* Z, l
                                                          int* info, T* work) {
     __shared__ T S[kB][kB + 1];
     __shared__ T Si[kB][kB + 1];
+    __shared__ T s_rcp[kDB];
     __shared__ int s_bad;
     const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
     T* Zb = Z + b * sz + k0 + (long long)k0 * ldz;
@@ -87,16 +126,17 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(int k0, int kb, T* Z, l
 #pragma unroll
             for (int i = 0; i < kDB; ++i) {
                 if (i < bw) {
-                    T d = __shfl(c[i], i, 64);
+                    T d = lane_bcast(c[i], i);
                     if (!(d > (T)0) || !isfinite(d)) {
                         if (bad == 0) bad = k0 + jb + i + 1;
                         d = 1;
                     }
                     const T r = sqrt(d), ri = (T)1 / r;
+                    if (lane == 0) s_rcp[i] = ri;
                     c[i] = lane == i ? r : (lane > i ? c[i] * ri : c[i]);
 #pragma unroll
                     for (int l = i + 1; l < kDB; ++l) {
-                        const T ril = __shfl(c[i], l, 64);  // R[i][jb + l]
+                        const T ril = lane_bcast(c[i], l);  // R[i][jb + l]
                         if (lane >= l) c[l] -= ril * c[i];
                     }
                 }
@@ -121,7 +161,7 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(int k0, int kb, T* Z, l
                     T s0 = S[jb + i][col];
 #pragma unroll
                     for (int k = 0; k < i; ++k) s0 -= S[jb + k][jb + i] * x[k];
-                    x[i] = s0 / S[jb + i][jb + i];
+                    x[i] = s0 * s_rcp[i];
                     S[jb + i][col] = x[i];
                 }
             }
@@ -144,7 +184,9 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(int k0, int kb, T* Z, l
         const int i = e % kb, j = e / kb;
         Zb[i + (long long)j * ldz] = (i <= j) ? S[i][j] : (T)0;
     }
-    lds_upper_inverse<T>(kb, S, Si);
+    if (tid >= kb && tid < kB) S[tid][tid] = 1;  // identity beyond the block
+    __syncthreads();
+    lds_upper_inverse<T>(S, Si);
     __syncthreads();
     T* wb = work + (long long)b * kB * kB;
     for (int e = tid; e < kB * kB; e += 256) {
@@ -169,8 +211,7 @@ __global__ __launch_bounds__(256) void trtri_diag_kernel(int n, const T* R, long
         S[i][j] = (i < kb && j < kb && i <= j) ? Rb[i + (long long)j * ldr] : (T)(i == j ? 1 : 0);
     }
     __syncthreads();
-    lds_upper_inverse<T>(kb, S, Si);
-    __syncthreads();
+    lds_upper_inverse<T>(S, Si);
     for (int e = tid; e < kb * kb; e += 256) {
         const int i = e % kb, j = e / kb;
         Ib[i + (long long)j * ldi] = Si[i][j];
