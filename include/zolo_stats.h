@@ -36,6 +36,26 @@ int zolo_stats_get(int index, char* name, int name_len, long long* launches, dou
 /* Number of entries (kernels seen since the last reset). */
 int zolo_stats_count(void);
 
+/* GEMM tile autotuning.  The FP64 MFMA GEMM has several tile shapes whose
+ * results are bit-identical (each output element sums the same products in
+ * the same order), so which one runs changes speed only.  For each shape
+ * class (device, transposes, triangular-operand flags, batch reduction,
+ * whether beta != 0, and floor(log2) of m, n and k) the first six calls run
+ * the three candidates twice each, in the order 0 1 2 2 1 0, on the caller's
+ * own data, each timed by a pair of HIP events that the library reads only
+ * once they have completed (it never waits on them).  Later calls of the
+ * class use the candidate with the least time per flop, where one replaces
+ * the fixed rule's tile only if it is more than 3% faster.  Split-K products
+ * keep the fixed tile.  The choices are process-wide and serialised by one
+ * lock.
+ * zolo_autotune_enable(0) makes every call use the fixed rule, on != 0
+ * turns tuning back on; without a call the environment variable
+ * ZOLO_AUTOTUNE=0 turns it off.  Returns 0. */
+int zolo_autotune_enable(int on);
+/* Forget every choice made so far: the next calls of each class time the
+ * candidates again.  Returns 0. */
+int zolo_autotune_reset(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,10 +20,12 @@
 #include "stats.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <mutex>
 #include <unordered_map>
 #include <type_traits>
 #include <cstdio>
+#include <cstdlib>
 
 namespace zolo {
 namespace {
@@ -1067,6 +1069,138 @@ hipError_t launch_dma(const GemmDescT<double>& desc, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Run-time tile choice for the DMA kernel (FP64 MFMA).  Its tile shapes
+// give bit-identical results (each output sums the same products in the same
+// k order; masked terms are exact zeros), so the first calls of a shape
+// class rotate through the candidates on real work, time each with events
+// that are read back only once complete (no synchronisation), and later
+// calls use the fastest per flop.  Split-K launches keep the static choice
+// (their piece boundaries depend on the tile).  ZOLO_AUTOTUNE=0 turns the
+// rotation off.
+constexpr int kTuneCand = 3;  // DMA 64 x 128, 64 x 64, 128 x 64
+struct TuneKey {
+    int dev, ta, tb, reduce, lm, ln, lk;
+    unsigned flags;
+    bool cin;
+    bool operator==(const TuneKey& o) const {
+        return dev == o.dev && ta == o.ta && tb == o.tb && reduce == o.reduce && lm == o.lm && ln == o.ln &&
+               lk == o.lk && flags == o.flags && cin == o.cin;
+    }
+};
+struct TuneKeyHash {
+    size_t operator()(const TuneKey& x) const {
+        return ((size_t)x.lm << 0) ^ ((size_t)x.ln << 6) ^ ((size_t)x.lk << 12) ^ ((size_t)x.flags << 18) ^
+               ((size_t)x.ta << 26) ^ ((size_t)x.tb << 27) ^ ((size_t)x.reduce << 28) ^ ((size_t)x.cin << 29) ^
+               ((size_t)x.dev << 32);
+    }
+};
+// Timed launches per class: each candidate twice, in the order 0 1 2 2 1 0,
+// so that a steady drift of the problem size along a sequence of calls (the
+// shrinking trailing matrix of a factorisation) weighs on every candidate
+// alike.
+constexpr int kTuneSlots = 2 * kTuneCand;
+constexpr int kTuneOrder[kTuneSlots] = {0, 1, 2, 2, 1, 0};
+// A candidate replaces the fixed rule's choice only when it is faster per
+// flop by more than this fraction (the rule is right for most classes, and
+// event timings of single launches vary by a few percent).
+constexpr double kTuneMargin = 0.03;
+struct TuneEntry {
+    int chosen = -1, launched = 0;
+    bool measured[kTuneSlots] = {};
+    float ms[kTuneSlots] = {};
+    double flops[kTuneSlots] = {};
+    hipEvent_t ev[kTuneSlots][2] = {};
+};
+std::mutex g_tune_mu;
+std::unordered_map<TuneKey, TuneEntry, TuneKeyHash> g_tune;
+
+std::atomic<int> g_tune_set{-1};  // zolo_autotune_enable; -1: from the environment
+
+bool autotune_on() {
+    const int v = g_tune_set.load(std::memory_order_relaxed);
+    if (v >= 0) return v != 0;
+    static const bool env = [] {
+        const char* e = getenv("ZOLO_AUTOTUNE");
+        return !(e && atoi(e) == 0);
+    }();
+    return env;
+}
+
+int ilog2(long long x) {
+    int l = 0;
+    while (x > 1) {
+        x >>= 1;
+        ++l;
+    }
+    return l;
+}
+
+hipError_t launch_dma_cand(int c, const GemmDescT<double>& d, hipStream_t s) {
+    if (c == 0) return launch_dma<64, 128>(d, s);
+    if (c == 1) return launch_dma<64, 64>(d, s);
+    return launch_dma<128, 64>(d, s);
+}
+
+hipError_t dispatch_dma_tuned(const GemmDescT<double>& d, int static_choice, hipStream_t s) {
+    if (!autotune_on() || d.splitk > 1) return launch_dma_cand(static_choice, d, s);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return launch_dma_cand(static_choice, d, s);
+    const TuneKey key{dev, d.transa, d.transb, d.reduce ? 1 : 0, ilog2(d.m), ilog2(d.n), ilog2(d.k), d.flags,
+                      d.Cin != nullptr && d.beta != 0.0};
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    TuneEntry& e = g_tune[key];
+    if (e.chosen >= 0) return launch_dma_cand(e.chosen, d, s);
+    int done = 0;
+    for (int q = 0; q < e.launched; ++q) {
+        if (!e.measured[q] && hipEventQuery(e.ev[q][1]) == hipSuccess &&
+            hipEventElapsedTime(&e.ms[q], e.ev[q][0], e.ev[q][1]) == hipSuccess)
+            e.measured[q] = true;
+        done += e.measured[q] ? 1 : 0;
+    }
+    if (done == kTuneSlots) {
+        double ms[kTuneCand] = {}, fl[kTuneCand] = {};
+        for (int q = 0; q < kTuneSlots; ++q) {
+            ms[kTuneOrder[q]] += e.ms[q];
+            fl[kTuneOrder[q]] += e.flops[q];
+        }
+        double score[kTuneCand];
+        for (int c = 0; c < kTuneCand; ++c) score[c] = ms[c] / (fl[c] > 0 ? fl[c] : 1.0);
+        int best = static_choice;
+        for (int c = 0; c < kTuneCand; ++c)
+            if (score[c] < score[best] && score[c] < (1.0 - kTuneMargin) * score[static_choice]) best = c;
+        e.chosen = best;
+        static const bool log = [] {
+            const char* v = getenv("ZOLO_AUTOTUNE_LOG");
+            return v && atoi(v) != 0;
+        }();
+        if (log) {
+            fprintf(stderr, "[zolo autotune] %c%c m~2^%d n~2^%d k~2^%d flags %u reduce %d cin %d:", d.transa ? 'T' : 'N',
+                    d.transb ? 'T' : 'N', key.lm, key.ln, key.lk, key.flags, key.reduce, (int)key.cin);
+            for (int q = 0; q < kTuneSlots; ++q)
+                fprintf(stderr, " %d:%.3fms/%.2fGF", kTuneOrder[q], e.ms[q], e.flops[q] * 1e-9);
+            fprintf(stderr, " -> %d (fixed rule %d)\n", best, static_choice);
+        }
+        for (int q = 0; q < kTuneSlots; ++q)
+            for (int h = 0; h < 2; ++h) (void)hipEventDestroy(e.ev[q][h]);
+        return launch_dma_cand(best, d, s);
+    }
+    if (e.launched < kTuneSlots) {
+        const int q = e.launched, c = kTuneOrder[q];
+        if (hipEventCreate(&e.ev[q][0]) != hipSuccess) return launch_dma_cand(static_choice, d, s);
+        if (hipEventCreate(&e.ev[q][1]) != hipSuccess) {
+            (void)hipEventDestroy(e.ev[q][0]);
+            return launch_dma_cand(static_choice, d, s);
+        }
+        ++e.launched;
+        e.flops[q] = gemm_flops(d);
+        hipError_t err = hipEventRecord(e.ev[q][0], s);
+        if (err == hipSuccess) err = launch_dma_cand(c, d, s);
+        if (err == hipSuccess) err = hipEventRecord(e.ev[q][1], s);
+        return err;
+    }
+    return launch_dma_cand(static_choice, d, s);
+}
+
 // Kernel and tile shape for a descriptor: 0/1 = MFMA gemm_kernel with
 // 64 x 64 / 64 x 128 tiles, 4 = dgemm_valu_kernel (128 x 128),
 // 5/6 = dgemm_dma_kernel with 64 x 128 / 64 x 64 tiles.  Measured on gfx950
@@ -1121,8 +1255,8 @@ hipError_t gemm_dispatch(const GemmDescT<T>& d, hipStream_t s) {
     const int t = pick_tile(d);
     if constexpr (sizeof(T) == 8) {
         if (t == 4) return launch_valu(d, s);
-        if (t == 5) return launch_dma<64, 128>(d, s);
-        if (t == 6) return launch_dma<64, 64>(d, s);
+        if (t == 5) return dispatch_dma_tuned(d, 0, s);
+        if (t == 6) return dispatch_dma_tuned(d, 1, s);
     }
     switch (t) {
         case 0: return launch_bm_bn<T, 64, 64>(d, s);
@@ -1168,3 +1302,18 @@ hipError_t gemm_split(GemmDesc d, double* work, size_t work_elems, hipStream_t s
 }
 
 }  // namespace zolo
+
+extern "C" int zolo_autotune_enable(int on) {
+    zolo::g_tune_set.store(on ? 1 : 0, std::memory_order_relaxed);
+    return 0;
+}
+
+extern "C" int zolo_autotune_reset(void) {
+    std::lock_guard<std::mutex> lock(zolo::g_tune_mu);
+    for (auto& kv : zolo::g_tune)
+        if (kv.second.chosen < 0)
+            for (int q = 0; q < kv.second.launched; ++q)
+                for (int h = 0; h < 2; ++h) (void)hipEventDestroy(kv.second.ev[q][h]);
+    zolo::g_tune.clear();
+    return 0;
+}

@@ -56,6 +56,7 @@ EXPORTS = ["zolo_default_opts", "zolo_create", "zolo_set_stream", "zolo_destroy"
            "zolo_pd_batched", "zolo_svd", "zolo_dgemm", "zolo_dpotrf_batched", "zolo_dtrtri_batched",
            "zolo_sgemm", "zolo_spotrf_batched", "zolo_strtri_batched", "zolo_structured_qr_batched",
            "zolo_stats_enable", "zolo_stats_reset", "zolo_stats_get", "zolo_stats_count",
+           "zolo_autotune_enable", "zolo_autotune_reset",
            "zolo_sketch_features", "zolo_surrogate_features", "zolo_mlp_stats", "zolo_mlp_work_elems",
            "zolo_mlp_forward", "zolo_mlp_loss", "zolo_mlp_backward", "zolo_mlp_adam", "zolo_mlp_train",
            "zolo_set_estimator", "zolo_choose_r"]
@@ -99,6 +100,8 @@ def load():
                                                c_int, c_int]  # M, ldm, strideM, R, ldr, strideR, batch, form_q
     lib.zolo_stats_enable.argtypes = [c_int]
     lib.zolo_stats_reset.argtypes = []
+    lib.zolo_autotune_enable.argtypes = [c_int]
+    lib.zolo_autotune_reset.argtypes = []
     lib.zolo_stats_count.argtypes = []
     lib.zolo_stats_get.argtypes = [c_int, ctypes.c_char_p, c_int, ctypes.POINTER(c_longlong), D, D, D]
     F = ctypes.c_float
@@ -141,6 +144,16 @@ def stats_enable(on=True):
 
 def stats_reset():
     load().zolo_stats_reset()
+
+
+def autotune_enable(on=True):
+    """Turn the GEMM tile autotuner on or off (results do not change)."""
+    load().zolo_autotune_enable(int(on))
+
+
+def autotune_reset():
+    """Forget the autotuner's tile choices."""
+    load().zolo_autotune_reset()
 
 
 def stats():

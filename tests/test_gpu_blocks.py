@@ -92,6 +92,37 @@ def test_gemm_lds_copy_kernel_shapes(z, ta, tb, m, n, k):
     assert np.abs(out - ref).max() <= 1e-13 * (k + 1) * 4
 
 
+@pytest.mark.parametrize("ta,tb,m,n,k", [(0, 0, 130, 258, 300), (1, 0, 131, 257, 518), (0, 1, 256, 384, 1000),
+                                          (1, 1, 192, 320, 160)])
+def test_gemm_autotune_bitwise(z, ta, tb, m, n, k):
+    # The autotuner runs every candidate tile shape of the LDS-copy kernel on
+    # the first calls of a shape class, then the fastest: every call must
+    # give the same bits, and all three shapes must have run.
+    from paper_1806_06204_amd import zolo
+    rng = np.random.default_rng(11 * m + n + k + 2 * ta + tb)
+    A = rng.standard_normal((2, k, m) if ta else (2, m, k))
+    B = rng.standard_normal((2, n, k) if tb else (2, k, n))
+    C = rng.standard_normal((2, m, n))
+    dA, dB, dC = dev(A), dev(B), dev(C)
+    zolo.autotune_enable(True)
+    zolo.autotune_reset()
+    zolo.stats_enable(True)
+    zolo.stats_reset()
+    try:
+        outs = [z.gemm(dA, dB, dC, transa=ta, transb=tb, alpha=0.7, beta=1.5).cpu().numpy() for _ in range(8)]
+        names = {nm for nm in zolo.stats() if nm.startswith("dgemm_dma<")}
+    finally:
+        zolo.stats_enable(False)
+    tag = ",%s,%s>" % ("T" if ta else "N", "T" if tb else "N")
+    assert names == {"dgemm_dma<%d,%d%s" % (bm, bn, tag) for bm, bn in ((64, 128), (64, 64), (128, 64))}
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    opA = np.swapaxes(A, 1, 2) if ta else A
+    opB = np.swapaxes(B, 1, 2) if tb else B
+    ref = 0.7 * opA @ opB + 1.5 * C
+    assert np.abs(outs[0] - ref).max() <= 1e-13 * (k + 1) * 4
+
+
 def test_gemm_vector_kernel_layout_identity(z):
     # Exact permutation products pin the 8 x 8 per-thread output layout.
     rng = np.random.default_rng(3)
