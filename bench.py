@@ -126,7 +126,8 @@ def bench_batched(args):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"{len(specs)} matrices, n~U[64,1024], m~U[n,2n], log10 kappa~U[2,12], "
                                   "l exact, r by the two-iteration policy", "count": len(specs),
-                      "batch_streams": args.batch_streams or 4},
+                      "batch_streams": args.batch_streams or 16,
+                      "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))},
            "matrices_per_s": len(specs) / dt,
            "r_histogram": {str(k): sum(1 for i in infos if i["r"] == k) for k in range(1, 9)},
            "max_bwd_err_sampled": max(e[0] for e in errs), "max_orth_err_sampled": max(e[1] for e in errs),
@@ -286,7 +287,9 @@ def main():
     ap.add_argument("--precision-study", action="store_true",
                     help="instead: FP64 vs mixed at kappa 1e4/1e8/1e12 (use with --r 3)")
     ap.add_argument("--batch-streams", type=int, default=0,
-                    help="with --batched: solves run at once (0: the library default, 4)")
+                    help="with --batched: solves run at once (0: the library default, 16)")
+    ap.add_argument("--hw-queues", type=int, default=16,
+                    help="with --batched: HIP hardware queues (GPU_MAX_HW_QUEUES, at most 24; 0: leave as is)")
     ap.add_argument("--batched", type=int, default=0,
                     help="instead: Zolo-PD of this many uneven matrices (n in [64,1024], m in [n,2n], "
                          "kappa log-uniform in [1e2,1e12]) in one zolo_pd_batched call")
@@ -295,6 +298,10 @@ def main():
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the Zolo-PD path has no multi-GPU mode", file=sys.stderr)
         sys.exit(2)
+    if args.batched and args.hw_queues > 0:
+        # One hardware queue per concurrent solve (the runtime reads this when
+        # it initialises, which importing torch does not yet do).
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(args.hw_queues, 24))
 
     import numpy as np
     import torch

@@ -97,10 +97,16 @@ typedef struct {
                             verified stop rule judges the result: an l above
                             sigma_min costs iterations, not accuracy. */
     int batch_streams;   /* zolo_pd_batched only: number of solves run at once,
-                            each on its own stream and host thread (0: 4; 1:
+                            each on its own stream and host thread (0: 16; 1:
                             one after another on the handle's stream).  Their
-                            cooperative panel launches share one stream, so
-                            at most one panel is in flight at any time. */
+                            panels of up to 2304 live rows run one workgroup
+                            per matrix on the solve's stream; larger panels
+                            are cooperative launches that share one stream,
+                            so at most one of those is in flight at any time.
+                            Solves overlap only as far as the HIP runtime has
+                            hardware queues for their streams
+                            (GPU_MAX_HW_QUEUES, 4 unless set; about 16 suits
+                            16 solves). */
     int reserved[7];
 } zolo_opts;
 

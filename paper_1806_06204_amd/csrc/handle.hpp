@@ -19,4 +19,7 @@ struct zolo_handle_s {
     // ordered against this handle's stream by the two events.
     hipStream_t panel_stream = nullptr;
     hipEvent_t ev_ready = nullptr, ev_done = nullptr;
+    // Solves of zolo_pd_batched (sequential or concurrent alike, so that
+    // both give the same bits): panels of few rows take one workgroup.
+    bool single_panels = false;
 };

@@ -74,6 +74,7 @@ struct QrWork {
     size_t splitk_elems = 0;
     hipStream_t panel_stream = nullptr;        // non-null: launch panels there (see run_panel)
     hipEvent_t ev_ready = nullptr, ev_done = nullptr;
+    bool single_panels = false;   // one workgroup per matrix for panels of few rows (see run_panel)
     double* Rd = nullptr;         // batch * npanels * kPanelNB^2 doubles (R diagonal blocks)
     double* S = nullptr;          // qr_s_elems(batch) doubles
     double* partials = nullptr;   // batch * 2 * maxG * 2 * kPanelNB doubles

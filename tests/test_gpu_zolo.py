@@ -245,14 +245,26 @@ def test_overestimated_l_is_reestimated(z, m, n, kappa, l_given, r):
 
 
 def test_batched_streams_match_sequential(z):
-    # Concurrent solves (several streams, one shared panel stream) give the
-    # same bits as one solve after another: every kernel is deterministic.
+    # Concurrent solves (several streams; single-workgroup panels on each
+    # solve's stream, cooperative ones on one shared panel stream) give the
+    # same bits as one solve after another: every kernel is deterministic and
+    # the panel geometry does not depend on the number of streams.  One
+    # matrix has more live rows than single-workgroup panels take.
     specs = W.batch_specs(count=10, seed=4200, nmin=40, nmax=700)
-    mats = [dev(W.svd_matrix(sp["m"], sp["n"], sp["kappa"], sp["seed_u"], sp["seed_v"])[0]) for sp in specs]
+    mats = [W.svd_matrix(sp["m"], sp["n"], sp["kappa"], sp["seed_u"], sp["seed_v"])[0] for sp in specs]
     ls = [1.0 / sp["kappa"] for sp in specs]
-    Qs1, Hs1, i1 = z.pd_batched(mats, alphas=[1.0] * len(mats), ls=ls, batch_streams=1)
-    Qs4, Hs4, i4 = z.pd_batched(mats, alphas=[1.0] * len(mats), ls=ls, batch_streams=4)
-    for a, b, c, d, x, y in zip(Qs1, Qs4, Hs1, Hs4, i1, i4):
-        assert x["status"] == 0 and y["status"] == 0 and x["kinds"] == y["kinds"]
-        assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
-        assert np.array_equal(c.cpu().numpy(), d.cpu().numpy())
+    for m, n, kappa in ((2048, 1024, 1e6), (2400, 200, 1e3)):
+        mats.append(W.svd_matrix(m, n, kappa, 31 + n, 32 + n)[0])
+        ls.append(1.0 / kappa)
+    dmats = [dev(A) for A in mats]
+    Qs1, Hs1, i1 = z.pd_batched(dmats, alphas=[1.0] * len(mats), ls=ls, batch_streams=1)
+    for streams in (4, 0):
+        Qs, Hs, inf = z.pd_batched(dmats, alphas=[1.0] * len(mats), ls=ls, batch_streams=streams)
+        for a, b, c, d, x, y in zip(Qs1, Qs, Hs1, Hs, i1, inf):
+            assert x["status"] == 0 and y["status"] == 0 and x["kinds"] == y["kinds"]
+            assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+            assert np.array_equal(c.cpu().numpy(), d.cpu().numpy())
+    for A, Q, H in zip(mats, Qs1, Hs1):
+        Q, H = Q.cpu().numpy(), H.cpu().numpy()
+        assert np.linalg.norm(A - Q @ H) <= BAR * np.linalg.norm(A)
+        assert np.linalg.norm(Q.T @ Q - np.eye(Q.shape[1])) <= BAR * math.sqrt(Q.shape[1])
