@@ -48,9 +48,11 @@ int zolo_stats_count(void);
  * the fixed rule's tile only if it is more than 3% faster.  Split-K products
  * keep the fixed tile.  The choices are process-wide and serialised by one
  * lock.
- * zolo_autotune_enable(0) makes every call use the fixed rule, on != 0
- * turns tuning back on; without a call the environment variable
- * ZOLO_AUTOTUNE=0 turns it off.  Returns 0. */
+ * Tuning is off by default (the fixed rule is as fast on the Zolo-PD
+ * workloads, and which kernel runs then does not depend on timing noise):
+ * zolo_autotune_enable(1) turns it on, zolo_autotune_enable(0) off again;
+ * without a call the environment variable ZOLO_AUTOTUNE=1 turns it on.
+ * Returns 0. */
 int zolo_autotune_enable(int on);
 /* Forget every choice made so far: the next calls of each class time the
  * candidates again.  Returns 0. */

@@ -1075,8 +1075,9 @@ hipError_t launch_dma(const GemmDescT<double>& desc, hipStream_t s) {
 // class rotate through the candidates on real work, time each with events
 // that are read back only once complete (no synchronisation), and later
 // calls use the fastest per flop.  Split-K launches keep the static choice
-// (their piece boundaries depend on the tile).  ZOLO_AUTOTUNE=0 turns the
-// rotation off.
+// (their piece boundaries depend on the tile).  Off unless ZOLO_AUTOTUNE=1
+// or zolo_autotune_enable(1): the fixed rule is as fast on the Zolo-PD
+// workloads, and keeps which kernel runs independent of timing noise.
 constexpr int kTuneCand = 3;  // DMA 64 x 128, 64 x 64, 128 x 64
 struct TuneKey {
     int dev, ta, tb, reduce, lm, ln, lk;
@@ -1121,7 +1122,7 @@ bool autotune_on() {
     if (v >= 0) return v != 0;
     static const bool env = [] {
         const char* e = getenv("ZOLO_AUTOTUNE");
-        return !(e && atoi(e) == 0);
+        return e && atoi(e) != 0;
     }();
     return env;
 }

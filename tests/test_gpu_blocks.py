@@ -113,6 +113,7 @@ def test_gemm_autotune_bitwise(z, ta, tb, m, n, k):
         names = {nm for nm in zolo.stats() if nm.startswith("dgemm_dma<")}
     finally:
         zolo.stats_enable(False)
+        zolo.autotune_enable(False)
     tag = ",%s,%s>" % ("T" if ta else "N", "T" if tb else "N")
     assert names == {"dgemm_dma<%d,%d%s" % (bm, bn, tag) for bm, bn in ((64, 128), (64, 64), (128, 64))}
     for o in outs[1:]:
