@@ -46,6 +46,11 @@ namespace {
 constexpr int kNB = kPanelNB;
 constexpr int kPT = 256;                 // threads per panel workgroup
 constexpr int kColsPerWave = kNB / 4;    // panel columns owned by each wave
+// Slab rows per lane loaded together in the column sweep: four when the
+// slab stays in global memory (latency of L2), one from LDS (more would cost
+// occupancy: 256 VGPRs against 144).
+template <bool InLds>
+constexpr int kRowUnroll = InLds ? 1 : 4;
 // s_waitcnt immediate (gfx9 encoding) that waits for vmcnt == 0 only:
 // vmcnt bits [3:0],[15:14] = 0, expcnt [6:4] = 7, lgkmcnt [11:8] = 15.
 constexpr int kWaitVmcnt0 = 0x0F70;
@@ -123,17 +128,25 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
         }
         const double ck = k > 0 ? s_coef[k] : 0.0;
         const int lo = max(r0, k > 0 ? k - 1 : 0);
-        for (int row = lo + lane; row < r1; row += 64) {
+        constexpr int U = kRowUnroll<InLds>;
+        // Rows are taken U at a time, all their loads first (the
+        // slab's rows are independent; this keeps several loads in flight),
+        // then the arithmetic and the stores row by row in increasing order,
+        // so the sums are accumulated in the same order as one row at a time.
+        auto load_row = [&](int row, double (&val)[kColsPerWave], double& vraw, double& xraw)
+                            __attribute__((always_inline)) {
             const int rl = row - r0;
-            // All loads of the row first, then arithmetic, then stores.
-            double val[kColsPerWave];
 #pragma unroll
             for (int q = 0; q < kColsPerWave; ++q) {
                 const int i = min(cw + q, nb - 1);
                 val[q] = X[rl + i * xld];
             }
-            const double vraw = k > 0 ? X[rl + (k - 1) * xld] : 0.0;
-            const double xraw = X[rl + k * xld];
+            vraw = k > 0 ? X[rl + (k - 1) * xld] : 0.0;
+            xraw = X[rl + k * xld];
+        };
+        auto finish_row = [&](int row, double (&val)[kColsPerWave], double vraw, double xraw)
+                              __attribute__((always_inline)) {
+            const int rl = row - r0;
             const double vprev = k > 0 ? (row == k - 1 ? 1.0 : vraw) : 0.0;
             const double xk = xraw - ck * vprev;
             const double xa = row > k ? xk : 0.0;  // column k below the pivot
@@ -150,6 +163,19 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
                 const int i = cw + q;
                 if (k > 0 && i > k && i < nb) X[rl + i * xld] = val[q];
             }
+        };
+        int row = lo + lane;
+        for (; row + 64 * (U - 1) < r1; row += 64 * U) {
+            double val[U][kColsPerWave], vraw[U], xraw[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) load_row(row + 64 * u, val[u], vraw[u], xraw[u]);
+#pragma unroll
+            for (int u = 0; u < U; ++u) finish_row(row + 64 * u, val[u], vraw[u], xraw[u]);
+        }
+        for (; row < r1; row += 64) {
+            double val[kColsPerWave], vraw, xraw;
+            load_row(row, val, vraw, xraw);
+            finish_row(row, val, vraw, xraw);
         }
         {
             // The 16 column sums of the wave in one transposing butterfly:
