@@ -159,7 +159,7 @@ int zolo_structured_qr_batched(zolo_handle h, int m, int n, const double* pivots
     const size_t need = 14 * 256 + sizeof(double) * (2 * qr_w_elems(n, batch) + qr_tb_elems(n, batch) +
                                                      qr_ts_elems(n, batch) + 2 * blk + qr_split_elems(n, batch) +
                                                      qr_s_elems(batch) + part) +
-                        sizeof(unsigned) * (size_t)batch * npanels + 64;
+                        sizeof(unsigned) * qr_flag_elems(m, e, batch, h->panel_coresident) + 64;
     if (int rc = grow(h, need)) return rc;
     QrWork w;
     w.W = (double*)bump(h->arena, off, sizeof(double) * qr_w_elems(n, batch));
@@ -172,7 +172,8 @@ int zolo_structured_qr_batched(zolo_handle h, int m, int n, const double* pivots
     w.Rd = (double*)bump(h->arena, off, sizeof(double) * blk);
     w.S = (double*)bump(h->arena, off, sizeof(double) * qr_s_elems(batch));
     w.partials = (double*)bump(h->arena, off, sizeof(double) * part);
-    w.counters = (unsigned*)bump(h->arena, off, sizeof(unsigned) * (size_t)batch * npanels);
+    w.flag_elems = qr_flag_elems(m, e, batch, h->panel_coresident);
+    w.flags = (unsigned*)bump(h->arena, off, sizeof(unsigned) * w.flag_elems);
     w.error_flag = (int*)bump(h->arena, off, 64);
     w.max_coresident = h->panel_coresident;
     hipStream_t st = h->stream;

@@ -78,7 +78,8 @@ struct QrWork {
     double* Rd = nullptr;         // batch * npanels * kPanelNB^2 doubles (R diagonal blocks)
     double* S = nullptr;          // qr_s_elems(batch) doubles
     double* partials = nullptr;   // batch * 2 * maxG * 2 * kPanelNB doubles
-    unsigned* counters = nullptr; // batch * npanels
+    unsigned* flags = nullptr;    // qr_flag_elems: per-workgroup panel sequence flags
+    size_t flag_elems = 0;
     int* error_flag = nullptr;    // 1 int
     int max_coresident = 0;       // workgroups of the panel kernel that fit at once
 };
@@ -105,6 +106,9 @@ inline size_t qr_partials_elems(int m, int e, int batch, int max_coresident) {
     if (G > cap) G = cap;
     if (G < 1) G = 1;
     return (size_t)batch * 2 * (G + 1) * 2 * kPanelNB;
+}
+inline size_t qr_flag_elems(int m, int e, int batch, int max_coresident) {
+    return qr_partials_elems(m, e, batch, max_coresident) / (4 * kPanelNB);
 }
 
 // M_b[0:m] = X (ld ldx; X null: leave the dense block), M_b[m:m+n] = pivots[b] * I, b < batch <= 16.

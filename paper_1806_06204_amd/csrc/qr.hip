@@ -37,6 +37,7 @@
 #include "stats.hpp"
 
 #include <cstdlib>
+#include <algorithm>
 #include <map>
 #include <mutex>
 
@@ -61,7 +62,8 @@ struct PanelArgs {
     double* T; long long st;             // T_b, kNB x kNB column-major
     double* Rd; long long srd;           // R diagonal block out, kNB x kNB
     double* partials;                    // [batch][2][G][2 kNB]
-    unsigned* counters;                  // [batch]
+    unsigned* flags;                     // [batch][G]: last column each workgroup published
+    unsigned seq;                        // flags of this panel's column k read seq + k + 1
     int* error_flag;
     unsigned spin_limit;
     int lds_stride;                      // InLds: leading dimension of the slab in LDS
@@ -109,7 +111,7 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
         s_w[kNB + tid] = 0.0;
     }
     __syncthreads();
-    unsigned* ctr = a.counters + b;
+    unsigned* flg = a.flags + (long long)b * a.G;
 
     for (int k = 0; k < nb; ++k) {
         // Phase A: reflector k-1 on the columns > k (rows >= k-1) and the dot
@@ -209,13 +211,15 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
         }
 
         // Phase B: publish, wait for the other slabs of this matrix, sum in order.
-        // Partials, counter and polls are device-coherent (agent-scope) atomics.
+        // Partials, flags and polls are device-coherent (agent-scope) atomics.
         // A workgroup barrier does not wait for outstanding global stores, so
-        // the storing wave (wave 0, the same wave that bumps the counter) waits
-        // for its partial stores to be acknowledged before the barrier; without
-        // that wait another workgroup can see the counter and read a stale
-        // partial.  No release/acquire fences: those would write back or
-        // invalidate the whole L2 on every column.
+        // the storing wave (wave 0, the same wave that then raises the
+        // workgroup's flag) waits for its partial stores to be acknowledged
+        // before the barrier; without that wait another workgroup can see the
+        // flag and read a stale partial.  No release/acquire fences: those
+        // would write back or invalidate the whole L2 on every column.  Each
+        // workgroup has a flag of its own (no atomic read-modify-write on one
+        // shared word), and thread t polls the flag of workgroup t.
         // One workgroup per matrix: its own sums are the totals.
         if (a.G == 1) {
             if (tid < nb) {
@@ -231,14 +235,12 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
                 __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
             }
             __syncthreads();
-            if (tid == 0) {
-                // The last workgroup to arrive learns it from the counter's old
-                // value and does not poll.
-                const unsigned target = (unsigned)(k + 1) * (unsigned)a.G;
-                const unsigned before = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned target = a.seq + (unsigned)k + 1u;
+            if (tid == 0) __hip_atomic_store(&flg[g], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int t = tid; t < a.G; t += kPT) {
+                if (t == g) continue;
                 unsigned spins = 0;
-                while (before + 1 < target &&
-                       __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                while (__hip_atomic_load(&flg[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
                     if (++spins > a.spin_limit) {
                         atomicOr(a.error_flag, 1);
                         break;
@@ -460,7 +462,19 @@ int lds_coresident(int R) {
     return cache[R] = per_cu * cu_count();
 }
 
-Geometry panel_geometry(int L, int batch, int max_coresident) {
+// Co-resident workgroups of the global-memory panel kernel.
+int global_coresident() {
+    static int v = [] {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)panel_kernel<false>, kPT, 0) !=
+            hipSuccess)
+            return 0;
+        return per_cu * cu_count();
+    }();
+    return v;
+}
+
+Geometry panel_geometry(int L, int batch) {
     // Slab in LDS when every workgroup of the launch can be resident with it.
     const int limit = lds_limit();
     if (limit > 0) {
@@ -476,7 +490,7 @@ Geometry panel_geometry(int L, int batch, int max_coresident) {
     const int target = panel_rows_target();
     int G = (L + target - 1) / target;
     if (G < 1) G = 1;
-    int cap = max_coresident / batch;
+    int cap = global_coresident() / batch;
     if (cap < 1) cap = 1;
     if (G > cap) G = cap;
     int rows = (L + G - 1) / G;
@@ -492,14 +506,13 @@ inline int live_rows(int m, int e, int p0, int nb) {
 
 }  // namespace
 
+// The most panel workgroups one launch of either variant can use (the LDS
+// variant with its smallest slab packs the most per CU); sizes the buffers
+// of per-workgroup partial sums and flags.
 int panel_max_coresident() {
-    int dev = 0, per_cu = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)panel_kernel<false>, kPT, 0) !=
-        hipSuccess)
-        return 0;
-    return per_cu * cus;
+    int v = global_coresident();
+    if (lds_limit() > 0) v = std::max(v, lds_coresident(64));
+    return v;
 }
 
 hipError_t stack_init(int m, int n, const double* X, long long ldx, double* M, long long ld, long long sm,
@@ -532,19 +545,22 @@ hipError_t run_panel(int m, int e, int p, int nb, double* M, long long ld, long 
                      long long stT, hipStream_t st) {
     const int p0 = p * kNB;
     const int L = live_rows(m, e, p0, nb);
-    Geometry geo = panel_geometry(L, batch, w.max_coresident);
+    Geometry geo = panel_geometry(L, batch);
     if (geo.G > 1 && w.single_panels && L <= kSinglePanelRows) {
         const int limit = lds_limit();
         const int max_rows = limit > 0 ? (limit - kStaticLds) / (kNB * (int)sizeof(double)) : 0;
         geo = {1, L, L <= max_rows};
     }
+    // The partial-sum and flag buffers hold max_coresident workgroups.
+    if ((long long)geo.G * batch > w.max_coresident && geo.G > 1) return hipErrorInvalidValue;
     PanelArgs pa;
     pa.L = L; pa.nb = nb; pa.G = geo.G; pa.rows_per_wg = geo.rows;
     pa.P = M + p0 + (long long)p0 * ld; pa.ld = ld; pa.sp = sm;
     pa.T = w.T + (long long)p * kNB * kNB; pa.st = stT;
     pa.Rd = w.Rd + (long long)p * kNB * kNB; pa.srd = stT;
     pa.partials = w.partials;
-    pa.counters = w.counters + (long long)p * batch;
+    pa.flags = w.flags;
+    pa.seq = (unsigned)p * kNB;
     pa.error_flag = w.error_flag;
     pa.spin_limit = 1u << 24;
     pa.lds_stride = geo.rows;
@@ -692,7 +708,7 @@ hipError_t structured_geqrf(int m, int e, int n, double* M, long long ld, long l
     const long long stT = (long long)npanels * kNB * kNB;
     const long long stb = (long long)nblocks * kQrBlock * kQrBlock;
     const long long sts = (long long)nsuper * kQrSuper * kQrSuper;
-    hipError_t err = hipMemsetAsync(w.counters, 0, sizeof(unsigned) * (size_t)batch * npanels, st);
+    hipError_t err = hipMemsetAsync(w.flags, 0, sizeof(unsigned) * w.flag_elems, st);
     if (err != hipSuccess) return err;
     for (int Q = 0; Q < nsuper; ++Q) {
         const int s0 = Q * kQrSuper;

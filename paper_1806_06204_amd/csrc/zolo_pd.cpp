@@ -118,7 +118,8 @@ Work layout(char* base, int m, int n, int rmax, int panel_coresident, bool mixed
     w.qr.S = ar.take<double>(qr_s_elems(rmax));
     w.qr.partials = ar.take<double>(std::max(qr_partials_elems(m, n, rmax, panel_coresident),
                                              qr_partials_elems(m, 0, 1, panel_coresident)));
-    w.qr.counters = ar.take<unsigned>((size_t)rmax * npanels);
+    w.qr.flag_elems = std::max(qr_flag_elems(m, n, rmax, panel_coresident), qr_flag_elems(m, 0, 1, panel_coresident));
+    w.qr.flags = ar.take<unsigned>(w.qr.flag_elems);
     w.qr.error_flag = w.iflags + 1;
     w.qr.max_coresident = panel_coresident;
     w.sk = ar.take<double>(sketch_scratch_elems(m, n));

@@ -104,6 +104,18 @@ def test_kappa_1e16_n512(z):
     assert info["kinds"][:2] == ["Q", "C"]
 
 
+def test_many_panel_workgroups(z):
+    # n = 4096, r = 4: the QR step's panels (4160 live rows) run 65 LDS-slab
+    # workgroups per matrix, 260 in all, more than the global-memory panel
+    # variant could hold at once; the per-workgroup partial sums and flags
+    # are sized for the larger of the two.
+    A = W.svd_matrix(4096, 4096, 1e12, 1400, 2400)[0]
+    Qp, H, info = z.pd(dev(A), alpha=1.0, l=1e-12, r=4, compute_errors=1)
+    print(f"  kinds={''.join(info['kinds'])} bwd={info['bwd_err']:.2e} orth={info['orth_err']:.2e}", flush=True)
+    assert info["status"] == 0 and info["kinds"][0] == "Q"
+    assert info["bwd_err"] <= BAR and info["orth_err"] <= BAR
+
+
 def test_estimated_alpha_and_l(z):
     A = W.sparse_pattern(256, bandwidth=16, p=0.01, seed=3001)
     Qp, H, info = z.pd(dev(A), compute_errors=1)
