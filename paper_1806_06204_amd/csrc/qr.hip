@@ -45,13 +45,14 @@ namespace zolo {
 namespace {
 
 constexpr int kNB = kPanelNB;
-constexpr int kPT = 256;                 // threads per panel workgroup
+constexpr int kRG = 2;                   // row groups: waves that split a column group's rows
+constexpr int kPT = 256 * kRG;           // threads per panel workgroup
 constexpr int kColsPerWave = kNB / 4;    // panel columns owned by each wave
-// Slab rows per lane loaded together in the column sweep: four when the
-// slab stays in global memory (latency of L2), one from LDS (more would cost
-// occupancy: 256 VGPRs against 144).
+// Slab rows per lane loaded together in the column sweep: two when the
+// slab stays in global memory (latency of L2; with two row groups, four
+// rows of each column group are in flight), one from LDS.
 template <bool InLds>
-constexpr int kRowUnroll = InLds ? 1 : 4;
+constexpr int kRowUnroll = InLds ? 1 : 2;
 // s_waitcnt immediate (gfx9 encoding) that waits for vmcnt == 0 only:
 // vmcnt bits [3:0],[15:14] = 0, expcnt [6:4] = 7, lgkmcnt [11:8] = 15.
 constexpr int kWaitVmcnt0 = 0x0F70;
@@ -90,6 +91,7 @@ template <bool InLds>
 __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
     extern __shared__ double smem[];
     __shared__ double s_d[kNB], s_pr[kNB], s_coef[kNB], s_z[kNB], s_w[2 * kNB];
+    __shared__ double s_wp[kRG][kNB];  // column sums of each row group
     __shared__ double s_T[kNB * (kNB + 1) / 2];  // upper T packed by columns: T[i][l] at l (l + 1) / 2 + i
     const int g = blockIdx.x % a.G, b = blockIdx.x / a.G;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -116,10 +118,11 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
     for (int k = 0; k < nb; ++k) {
         // Phase A: reflector k-1 on the columns > k (rows >= k-1) and the dot
         // products of column k below the pivot with every panel column.  Wave
-        // w owns columns 16 w .. 16 w + 15; its index is made scalar so that
-        // every per-column condition is uniform.
+        // w owns columns 16 (w % 4) .. 16 (w % 4) + 15 over the rows of row
+        // group w / 4 (every kRG-th block of 64 rows); its index is made
+        // scalar so that every per-column condition is uniform.
         const int wv = __builtin_amdgcn_readfirstlane(wave);
-        const int cw = wv * kColsPerWave;
+        const int cw = (wv & 3) * kColsPerWave, rg = wv >> 2;
         double acc[kColsPerWave], cq[kColsPerWave];
 #pragma unroll
         for (int q = 0; q < kColsPerWave; ++q) {
@@ -166,15 +169,16 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
                 if (k > 0 && i > k && i < nb) X[rl + i * xld] = val[q];
             }
         };
-        int row = lo + lane;
-        for (; row + 64 * (U - 1) < r1; row += 64 * U) {
+        constexpr int S = 64 * kRG;  // row stride of a lane
+        int row = lo + 64 * rg + lane;
+        for (; row + S * (U - 1) < r1; row += S * U) {
             double val[U][kColsPerWave], vraw[U], xraw[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) load_row(row + 64 * u, val[u], vraw[u], xraw[u]);
+            for (int u = 0; u < U; ++u) load_row(row + S * u, val[u], vraw[u], xraw[u]);
 #pragma unroll
-            for (int u = 0; u < U; ++u) finish_row(row + 64 * u, val[u], vraw[u], xraw[u]);
+            for (int u = 0; u < U; ++u) finish_row(row + S * u, val[u], vraw[u], xraw[u]);
         }
-        for (; row < r1; row += 64) {
+        for (; row < r1; row += S) {
             double val[kColsPerWave], vraw, xraw;
             load_row(row, val, vraw, xraw);
             finish_row(row, val, vraw, xraw);
@@ -197,9 +201,16 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
             t += __shfl_xor(t, 2, 64);
             t += __shfl_xor(t, 1, 64);
             const int i = cw + ((lane >> 2) & 15);
-            if ((lane & 3) == 0 && i < nb) s_w[i] = t;
+            if ((lane & 3) == 0 && i < nb) s_wp[rg][i] = t;
         }
         __syncthreads();
+        // The row groups' sums, added in a fixed order.
+        if (tid < nb) {
+            double t = s_wp[0][tid];
+#pragma unroll
+            for (int q = 1; q < kRG; ++q) t += s_wp[q][tid];
+            s_w[tid] = t;
+        }
         // The pivot row after the update, read back by the workgroup that owns
         // it (its slots stay zero elsewhere): columns > k were stored above,
         // columns < k are unchanged and column k is recomputed.
@@ -422,7 +433,7 @@ int panel_rows_target() {
 // 3.34 s with cooperative panels, 2.81 s with single-workgroup panels.
 constexpr int kSinglePanelRows = 2304;
 
-constexpr int kStaticLds = (6 * kNB + kNB * (kNB + 1) / 2) * 8 + 256;
+constexpr int kStaticLds = (6 * kNB + kRG * kNB + kNB * (kNB + 1) / 2) * 8 + 256;
 
 int lds_limit() {
     static int v = [] {
