@@ -277,6 +277,26 @@ def test_structured_qr_many_slabs(z, m, n, batch):
             assert np.abs(R[b] * s[:, None] - Rl).max() <= 1e-12 * np.abs(Rl).max(), (rep, b)
 
 
+def test_structured_qr_global_slabs(z):
+    # 12064 live rows per panel and 8 matrices: the slabs do not fit in LDS
+    # with every workgroup resident, so the panels run the global-memory
+    # variant (32 workgroups per matrix, 377 rows each) with the cooperative
+    # exchange.
+    rng = np.random.default_rng(12000)
+    m, n, batch = 12000, 128, 8
+    pivots = [0.5 ** b for b in range(batch)]
+    Y = rng.standard_normal((batch, m, n)) / np.sqrt(m)
+    Q, R = z.structured_qr(dev(Y), pivots, form_q=True)
+    Q, R = Q.cpu().numpy(), R.cpu().numpy()
+    for b, p in enumerate(pivots):
+        S = np.vstack([Y[b], p * np.eye(n)])
+        assert np.linalg.norm(Q[b].T @ Q[b] - np.eye(n)) <= 1e-14 * n, b
+        assert np.linalg.norm(Q[b] @ R[b] - S) <= 1e-14 * n * np.linalg.norm(S), b
+        Rl = np.linalg.qr(S, mode="r")
+        s = np.sign(np.diag(R[b])) * np.sign(np.diag(Rl))
+        assert np.abs(R[b] * s[:, None] - Rl).max() <= 1e-12 * np.abs(Rl).max(), b
+
+
 @pytest.mark.parametrize("m,n", [(100, 100), (333, 129), (64, 1)])
 def test_plain_qr(z, m, n):
     rng = np.random.default_rng(3 * m + n)
