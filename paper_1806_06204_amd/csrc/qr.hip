@@ -92,6 +92,7 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
     extern __shared__ double smem[];
     __shared__ double s_d[kNB], s_pr[kNB], s_coef[kNB], s_z[kNB], s_w[2 * kNB];
     __shared__ double s_wp[kRG][kNB];  // column sums of each row group
+    __shared__ double s_tau;             // tau of the column whose T column is still to be formed
     __shared__ double s_T[kNB * (kNB + 1) / 2];  // upper T packed by columns: T[i][l] at l (l + 1) / 2 + i
     const int g = blockIdx.x % a.G, b = blockIdx.x / a.G;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -114,6 +115,32 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
     }
     __syncthreads();
     unsigned* flg = a.flags + (long long)b * a.G;
+    // Column kk of T: T[0:kk, kk] = -tau T[0:kk, 0:kk] z, T[kk][kk] = tau,
+    // with z = V[:, 0:kk]^T v_kk (s_z) and tau (s_tau) of column kk; by
+    // threads 64 .. 64 + kk of the first workgroup of each matrix (the only
+    // one that keeps T).  It runs during the next column's exchange, while
+    // wave 0 waits for the other workgroups, so that this workgroup, which
+    // every other one waits for, does not publish its partial sums late.
+    auto t_update = [&](int kk) __attribute__((always_inline)) {
+        const int j = tid - 64;
+        if (g != 0 || j < 0 || j > kk) return;
+        const double tk = s_tau;
+        if (j < kk) {
+            // Four partial sums break the dependent chain of LDS reads.
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            int l = j;
+            for (; l + 3 < kk; l += 4) {
+                s0 += s_T[l * (l + 1) / 2 + j] * s_z[l];
+                s1 += s_T[(l + 1) * (l + 2) / 2 + j] * s_z[l + 1];
+                s2 += s_T[(l + 2) * (l + 3) / 2 + j] * s_z[l + 2];
+                s3 += s_T[(l + 3) * (l + 4) / 2 + j] * s_z[l + 3];
+            }
+            for (; l < kk; ++l) s0 += s_T[l * (l + 1) / 2 + j] * s_z[l];
+            s_T[kk * (kk + 1) / 2 + j] = -tk * ((s0 + s1) + (s2 + s3));
+        } else {
+            s_T[kk * (kk + 1) / 2 + kk] = tk;
+        }
+    };
 
     for (int k = 0; k < nb; ++k) {
         // Phase A: reflector k-1 on the columns > k (rows >= k-1) and the dot
@@ -233,6 +260,7 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
         // shared word), and thread t polls the flag of workgroup t.
         // One workgroup per matrix: its own sums are the totals.
         if (a.G == 1) {
+            if (k > 0) t_update(k - 1);
             if (tid < nb) {
                 s_d[tid] = s_w[tid];
                 s_pr[tid] = s_w[kNB + tid];
@@ -248,6 +276,7 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
             __syncthreads();
             const unsigned target = a.seq + (unsigned)k + 1u;
             if (tid == 0) __hip_atomic_store(&flg[g], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (k > 0) t_update(k - 1);
             for (int t = tid; t < a.G; t += kPT) {
                 if (t == g) continue;
                 unsigned spins = 0;
@@ -306,26 +335,8 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
             if (tid > k) s_coef[tid] = tau * w;
             if (tid < k) s_z[tid] = w;
         }
+        if (g == 0 && tid == 0) s_tau = tau;  // its T column is formed during the next exchange
         __syncthreads();
-        // T[0:k, k] = -tau T[0:k, 0:k] z;  T[k][k] = tau (T is kept by the
-        // first workgroup of each matrix only).
-        if (g == 0) {
-            if (tid < k) {
-                // Four partial sums break the dependent chain of LDS reads.
-                double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-                int l = tid;
-                for (; l + 3 < k; l += 4) {
-                    s0 += s_T[l * (l + 1) / 2 + tid] * s_z[l];
-                    s1 += s_T[(l + 1) * (l + 2) / 2 + tid] * s_z[l + 1];
-                    s2 += s_T[(l + 2) * (l + 3) / 2 + tid] * s_z[l + 2];
-                    s3 += s_T[(l + 3) * (l + 4) / 2 + tid] * s_z[l + 3];
-                }
-                for (; l < k; ++l) s0 += s_T[l * (l + 1) / 2 + tid] * s_z[l];
-                s_T[k * (k + 1) / 2 + tid] = -tau * ((s0 + s1) + (s2 + s3));
-            } else if (tid == k) {
-                s_T[k * (k + 1) / 2 + k] = tau;
-            }
-        }
         // Phase D: column k: R entry on row k-1, beta on the pivot, v below.
         for (int row = max(r0, k > 0 ? k - 1 : 0) + tid; row < r1; row += kPT) {
             const int rl = row - r0;
@@ -336,6 +347,8 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
         if (tid < kNB) s_w[kNB + tid] = 0.0;  // pivot-row slots of the next column
         __syncthreads();
     }
+    t_update(nb - 1);  // the last column's T column (s_z, s_tau published by the loop's last barrier)
+    __syncthreads();
     // Save the R diagonal block; make V's top block explicit (1 on the
     // diagonal, 0 above) so the GEMMs can use the stored panel as V.
     double* Rd = a.Rd + b * a.srd;
