@@ -92,6 +92,42 @@ def cpu_baseline(n_sample, kappa, r):
             "seconds": dt, "schedule": "".join(info["kinds"])}
 
 
+def bench_gemm_classes(args):
+    """The two GEMM classes that dominate the solve, alone: a rank-256 update
+    C -= A B (12288 x 6144 x 256, batch 8, Cin = C; the trailing updates of
+    the factorisations) and an 8192^3 product (long k).  Prints the time and
+    rate of each (for counter runs under rocprofv3)."""
+    import ctypes
+    import torch
+    from paper_1806_06204_amd import zolo
+    lib = zolo.load()
+    z = zolo.Zolo()
+    P = ctypes.c_void_p
+    out = {}
+    for (m, n, k, b, beta) in [(12288, 6144, 256, 8, 1.0), (8192, 8192, 8192, 1, 0.0)]:
+        g = torch.Generator(device="cuda:0").manual_seed(m + k)
+        A = torch.randn(b, k, m, dtype=torch.float64, device="cuda:0", generator=g)
+        B = torch.randn(b, n, k, dtype=torch.float64, device="cuda:0", generator=g)
+        C = torch.randn(b, n, m, dtype=torch.float64, device="cuda:0", generator=g)
+        call = (z.h, 0, 0, m, n, k, -1.0, P(A.data_ptr()), m, m * k, P(B.data_ptr()), k, k * n, beta,
+                P(C.data_ptr()), m, m * n, b)
+        for _ in range(max(1, args.warmup)):
+            if lib.zolo_dgemm(*call):
+                raise RuntimeError("zolo_dgemm failed")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            lib.zolo_dgemm(*call)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        key = f"{m}x{n}x{k}x{b}" + ("_cin" if beta else "")
+        out[key] = {"ms": dt * 1e3, "tflops": 2.0 * m * n * k * b / dt / 1e12}
+        print(f"[bench] gemm {key}: {dt * 1e3:.3f} ms, {out[key]['tflops']:.1f} TFLOP/s", file=sys.stderr, flush=True)
+        del A, B, C
+    print(json.dumps({"gemm_classes": out}), flush=True)
+    z.close()
+
+
 def bench_batched(args):
     """Uneven batch: one zolo_pd_batched call per step, l exact, r by the policy."""
     import numpy as np
@@ -290,6 +326,8 @@ def main():
                     help="with --batched: solves run at once (0: the library default, 16)")
     ap.add_argument("--hw-queues", type=int, default=16,
                     help="with --batched: HIP hardware queues (GPU_MAX_HW_QUEUES, at most 24; 0: leave as is)")
+    ap.add_argument("--gemm-classes", action="store_true",
+                    help="instead: time the rank-256 update and the 8192^3 product alone")
     ap.add_argument("--batched", type=int, default=0,
                     help="instead: Zolo-PD of this many uneven matrices (n in [64,1024], m in [n,2n], "
                          "kappa log-uniform in [1e2,1e12]) in one zolo_pd_batched call")
@@ -310,6 +348,8 @@ def main():
 
     if args.batched:
         return bench_batched(args)
+    if args.gemm_classes:
+        return bench_gemm_classes(args)
     if args.precision_study:
         return bench_precision_study(args)
     if args.learned:
