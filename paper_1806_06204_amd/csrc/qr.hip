@@ -12,8 +12,9 @@
 // pivoting on the small rows p I first (identity block on top) loses row-wise
 // backward stability when p is tiny, e.g. 1e-10 backward error at kappa = 1e8.
 //
-// Panel: one cooperative launch per panel factors all b together.  Each
-// matrix gets G workgroups, each owning a slab of the panel's live rows.  For
+// Panel: one launch per panel factors all b together (a cooperative launch
+// when a matrix takes more than one workgroup).  Each matrix gets G
+// workgroups, each owning a slab of the panel's live rows.  For
 // column k a workgroup applies reflector k-1 to its rows and, in the same pass,
 // accumulates the dot products of column k (below the pivot) with every panel
 // column and picks up the pivot row; one cross-workgroup reduction of these
@@ -164,7 +165,7 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
         // Rows are taken U at a time, all their loads first (the
         // slab's rows are independent; this keeps several loads in flight),
         // then the arithmetic and the stores row by row in increasing order,
-        // so the sums are accumulated in the same order as one row at a time.
+        // so each lane accumulates its rows in the same order as one at a time.
         auto load_row = [&](int row, double (&val)[kColsPerWave], double& vraw, double& xraw)
                             __attribute__((always_inline)) {
             const int rl = row - r0;
