@@ -90,3 +90,12 @@ def test_learned_layout_constants(lib):
     from paper_1806_06204_amd import zolo
     assert (zolo.NF, zolo.MLP_NPARAMS, zolo.MLP_NSTATS) == (OL.NF, OL.N_PARAMS, OL.N_STATS)
     assert lib.zolo_mlp_work_elems(100) >= (OL.NF + 4 * OL.NH) * 100
+
+
+def test_autotune_switch_is_host_only(lib):
+    # Turning the GEMM tile autotuner on and off and forgetting its choices
+    # touch only host state (no device is needed); both calls return 0.
+    assert lib.zolo_autotune_enable(1) == 0
+    assert lib.zolo_autotune_reset() == 0
+    assert lib.zolo_autotune_enable(0) == 0
+    assert lib.zolo_autotune_reset() == 0
