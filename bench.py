@@ -14,6 +14,8 @@ tflops_executed uses the flops the library's kernels actually perform.
 roofline: the kernel with the largest share of GPU time, from HIP events
 recorded around each of its launches on the library's stream during the timed
 steps: achieved = (its algorithmic flops / launch) / (its mean duration).
+roofline_runner_up: the same for the second kernel when its share is within
+10 % of the first (two such kernels trade places from run to run).
 cpu_baseline: the CPU FP64 oracle on a bounded sample of the same workload
 (a smaller n, same kappa and r), timed on this host.
 """
@@ -311,7 +313,7 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--kappa", type=float, default=1e16)
     ap.add_argument("--r", type=int, default=8)
-    ap.add_argument("--cpu-sample", type=int, default=640)
+    ap.add_argument("--cpu-sample", type=int, default=832)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first copy this many MiB device to device (a dispatch of known traffic for "
@@ -394,10 +396,25 @@ def main():
           file=sys.stderr, flush=True)
 
     # Dominant kernel by GPU time.
-    name, (launches, ms, flops, nbytes) = max(st.items(), key=lambda kv: kv[1][1])
+    ranked = sorted(st.items(), key=lambda kv: -kv[1][1])
+    name, (launches, ms, flops, nbytes) = ranked[0]
     achieved = (flops / launches) / (ms / launches * 1e-3) / 1e12
     traffic = measured_traffic(name)
     gpu_ms_total = sum(v[1] for v in st.values()) / args.steps
+
+    def roofline_of(kname, kst):
+        l, t, f, b = kst
+        a = (f / l) / (t / l * 1e-3) / 1e12
+        tr = measured_traffic(kname)
+        return {"bound": "mfma", "kernel": kname, "achieved": a, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": a / FP64_PEAK_TFLOPS, "traffic": tr["bytes_per_launch"] if tr else None,
+                "traffic_source": tr["file"] if tr else "no counter summary for the current source",
+                "ms_per_step": t / args.steps, "launches_per_step": l / args.steps, "mean_launch_ms": t / l}
+    # The second kernel by GPU time, when it is within 10 % of the first (two
+    # kernels that close trade places from run to run).
+    runner_up = None
+    if len(ranked) > 1 and ranked[1][1][1] >= 0.9 * ms and ranked[1][1][2] > 0:
+        runner_up = roofline_of(*ranked[1])
 
     # Accuracy of the same solve (separate call, errors computed on the GPU),
     # and sampled entries of H against V diag(sigma) V^T.
@@ -460,6 +477,7 @@ def main():
                      "algorithmic_GB_s": (nbytes / launches) / (ms / launches * 1e-3) / 1e9,
                      "launches_per_step": launches / args.steps,
                      "mean_launch_ms": ms / launches},
+        "roofline_runner_up": runner_up,
         "mixed": mixed,
         "cpu_baseline": cpu,
     }
