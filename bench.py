@@ -91,7 +91,193 @@ def cpu_baseline(n_sample, kappa, r):
     return {"value": f / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
             "sample": f"oracle zolo_pd on one {n_sample}x{n_sample} matrix of the same generator "
                       f"(kappa={kappa:g}, r={r}), {''.join(info['kinds'])} schedule, {dt:.1f} s",
-            "seconds": dt, "schedule": "".join(info["kinds"])}
+            "seconds": dt, "schedule": "".join(info["kinds"]), "cpu_model": cpu_model(),
+            "host_cpus": os.cpu_count()}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def timed_pd(z, A, reps, **kw):
+    """Median wall time (ms) of `reps` solves after one warm-up, and the info
+    of the last."""
+    import torch
+    z.pd(A, **kw)
+    times, info = [], None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, info = z.pd(A, **kw)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+    times.sort()
+    return times[len(times) // 2], info
+
+
+def bench_r_sweep(args):
+    """FP64 Zolo-PD of the headline matrix for several degrees r (r = 1 is
+    QDWH-PD, Section 2.1), each at the 1e-13 bar: schedule, time, TFLOP/s in
+    the paper's and in the executed flop count, errors, and the library's
+    predicted time; then the solve with r chosen by least predicted time."""
+    import numpy as np
+    import torch
+    from paper_1806_06204_amd import workloads as W
+    from paper_1806_06204_amd import zolo
+    n, kappa = args.n, args.kappa
+    print(f"[bench] generating {n}x{n} kappa={kappa:g} input", file=sys.stderr, flush=True)
+    A = zolo.to_device(W.svd_matrix(n, n, kappa, 1000 + 1, 2000 + 1)[0])
+    z = zolo.Zolo()
+    rows = []
+    for r in args.sweep_r:
+        ms, info = timed_pd(z, A, args.steps, alpha=1.0, l=1.0 / kappa, r=r)
+        _, _, e = z.pd(A, alpha=1.0, l=1.0 / kappa, r=r, compute_errors=1)
+        pk, pms = zolo.predict(1.0 / kappa, r, n, n)
+        row = {"r": r, "ms": ms, "schedule": "".join(info["kinds"]), "iters": info["iters"],
+               "checks": info["checks"], "tflops_paper": info["flops_paper"] / ms / 1e9,
+               "tflops_executed": info["flops_exec"] / ms / 1e9, "bwd_err": e["bwd_err"], "orth_err": e["orth_err"],
+               "meets_1e-13": bool(e["status"] == 0 and e["bwd_err"] <= 1e-13 and e["orth_err"] <= 1e-13),
+               "stage_ms": {"qr": info["t_stage_ms"][1], "chol": info["t_stage_ms"][2],
+                            "checks": info["t_stage_ms"][3], "H": info["t_stage_ms"][4]},
+               "predicted_schedule": pk, "predicted_ms": pms}
+        rows.append(row)
+        print(f"[bench] r={r}: {row}", file=sys.stderr, flush=True)
+    ms_t, info_t = timed_pd(z, A, args.steps, alpha=1.0, l=1.0 / kappa, r_policy=1)
+    _, _, e = z.pd(A, alpha=1.0, l=1.0 / kappa, r_policy=1, compute_errors=1)
+    base = next((x for x in rows if x["r"] == 8), None)
+    chosen = {"r": info_t["r"], "ms": ms_t, "schedule": "".join(info_t["kinds"]), "bwd_err": e["bwd_err"],
+              "orth_err": e["orth_err"],
+              "meets_1e-13": bool(e["status"] == 0 and e["bwd_err"] <= 1e-13 and e["orth_err"] <= 1e-13),
+              "speedup_vs_r8": (base["ms"] / ms_t) if base else None}
+    out = {"metric": "Zolo-PD FP64 time per degree r (r = 1: QDWH-PD) at bwd err <= 1e-13", "n_gpus": 1,
+           "steps": args.steps, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"{n}x{n} A = U diag(sigma) V^T, Haar U,V, sigma log-spaced 1..1/{kappa:g}, "
+                                  "alpha=1, l=1/kappa, verified stop", "n": n, "kappa": kappa},
+           "rows": rows, "least_predicted_time": chosen}
+    print(json.dumps(out), flush=True)
+    z.close()
+
+
+def bench_svd(args):
+    """Zolo-SVD (Algorithm 2) of the n x n kappa = 1e16 generator matrix: the
+    polar decomposition, the eigensolver and U = Qp V timed apart, accuracy
+    against the exact singular values and the paper's Res / OrthL / OrthR
+    (Section 4.1, eq. (13))."""
+    import numpy as np
+    import torch
+    from paper_1806_06204_amd import workloads as W
+    from paper_1806_06204_amd import zolo
+    n, kappa = args.n, args.kappa
+    print(f"[bench] generating {n}x{n} kappa={kappa:g} input", file=sys.stderr, flush=True)
+    A_np, U0, sig, V0 = W.svd_matrix(n, n, kappa, 1000 + 3, 2000 + 3)
+    A = zolo.to_device(A_np)
+    z = zolo.Zolo()
+    z.svd(A, alpha=1.0, l=1.0 / kappa, r=args.r)            # warm-up
+    rows = []
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        U, S, V, info = z.svd(A, alpha=1.0, l=1.0 / kappa, r=args.r)
+        torch.cuda.synchronize()
+        rows.append(((time.perf_counter() - t0) * 1e3, info))
+    rows.sort(key=lambda x: x[0])
+    ms, info = rows[len(rows) // 2]
+    At, Ut, Vt = (torch.from_numpy(np.ascontiguousarray(x)) for x in (A_np, U.cpu().numpy(), V.cpu().numpy()))
+    St = torch.from_numpy(S)
+    res = float(torch.linalg.norm(At - (Ut * St) @ Vt.T)) / float(S.max())
+    eye = torch.eye(n, dtype=torch.float64)
+    orth_l = float(torch.linalg.norm(eye - Ut.T @ Ut)) / n
+    orth_r = float(torch.linalg.norm(eye - Vt.T @ Vt)) / n
+    out = {"metric": "Zolo-SVD time (PD + eigensolver + U = Qp V) and accuracy", "n_gpus": 1, "steps": args.steps,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"{n}x{n} A = U diag(sigma) V^T, Haar U,V, sigma log-spaced 1..1/{kappa:g}, "
+                                  f"alpha=1, l=1/kappa, r={args.r}", "n": n, "kappa": kappa, "r": args.r},
+           "ms": ms, "pd_ms": sum(info["t_stage_ms"][:5]), "eig_ms": info["t_stage_ms"][5],
+           "u_ms": info["t_stage_ms"][6], "schedule": "".join(info["kinds"]),
+           "max_abs_sigma_err": float(np.max(np.abs(S - sig))), "res_paper": res, "orth_l_paper": orth_l,
+           "orth_r_paper": orth_r}
+    print(json.dumps(out), flush=True)
+    z.close()
+
+
+def bench_qr_ablation(args):
+    """Section 3.1 / Table 2: the structured QR of the stacked [X; I]
+    (m + 64 live rows per panel) against the same blocked Householder QR
+    applied to [X; I] as a dense (m + n) x n matrix, GEQRF and ORGQR timed
+    apart (ORGQR = factor-and-form minus factor), for m = n in args.ablation_n;
+    then the QR-type step inside Zolo-PD at the headline size with both."""
+    import ctypes
+    import numpy as np
+    import torch
+    from paper_1806_06204_amd import workloads as W
+    from paper_1806_06204_amd import zolo
+    lib = zolo.load()
+    z = zolo.Zolo()
+    P = ctypes.c_void_p
+    rows = []
+    for n in args.ablation_n:
+        m = n
+        g = torch.Generator(device="cuda:0").manual_seed(n)
+        X = torch.randn(n, m, dtype=torch.float64, device="cuda:0", generator=g)   # column-major m x n
+        Mbuf = torch.zeros(n, m + n, dtype=torch.float64, device="cuda:0")
+        R = torch.empty(n, n, dtype=torch.float64, device="cuda:0")
+        piv = (ctypes.c_double * 1)(1.0)
+        eye = torch.eye(n, dtype=torch.float64, device="cuda:0")
+
+        def run(dense, form_q):
+            Mbuf[:, :m] = X
+            if dense:
+                Mbuf[:, m:] = eye            # [X; I] as an ordinary (m + n) x n matrix
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if dense:
+                rc = lib.zolo_structured_qr_batched(z.h, m + n, n, None, P(Mbuf.data_ptr()), m + n, (m + n) * n,
+                                                    P(R.data_ptr()), n, n * n, 1, form_q)
+            else:
+                rc = lib.zolo_structured_qr_batched(z.h, m, n, piv, P(Mbuf.data_ptr()), m + n, (m + n) * n,
+                                                    P(R.data_ptr()), n, n * n, 1, form_q)
+            torch.cuda.synchronize()
+            if rc:
+                raise RuntimeError(f"zolo_structured_qr_batched failed ({rc})")
+            return (time.perf_counter() - t0) * 1e3
+
+        row = {"M": f"{m + n}x{n}"}
+        for name, dense in (("structured", False), ("dense", True)):
+            run(dense, 0)
+            f = sorted(run(dense, 0) for _ in range(args.steps))[args.steps // 2]
+            fq = sorted(run(dense, 1) for _ in range(args.steps))[args.steps // 2]
+            Rh = R.cpu().numpy()
+            row[name] = {"geqrf_ms": f, "orgqr_ms": fq - f, "total_ms": fq}
+        row["geqrf_speedup"] = row["dense"]["geqrf_ms"] / row["structured"]["geqrf_ms"]
+        row["orgqr_speedup"] = row["dense"]["orgqr_ms"] / row["structured"]["orgqr_ms"]
+        rows.append(row)
+        print(f"[bench] {row}", file=sys.stderr, flush=True)
+        del X, Mbuf, R, eye
+    # Inside Zolo-PD: the QR-type step at the headline size (first step, r = 8).
+    n, kappa = args.n, args.kappa
+    A = zolo.to_device(W.svd_matrix(n, n, kappa, 1000 + 1, 2000 + 1)[0])
+    pd = {}
+    for name, var in (("structured", 0), ("dense", 1)):
+        ms, info = timed_pd(z, A, max(1, args.steps // 2), alpha=1.0, l=1.0 / kappa, r=args.r, qr_variant=var)
+        _, _, e = z.pd(A, alpha=1.0, l=1.0 / kappa, r=args.r, qr_variant=var, compute_errors=1)
+        nq = info["kinds"].count("Q")
+        pd[name] = {"ms": ms, "schedule": "".join(info["kinds"]), "qr_step_ms": info["t_stage_ms"][1] / max(1, nq),
+                    "bwd_err": e["bwd_err"], "orth_err": e["orth_err"]}
+        print(f"[bench] zolo_pd {name}: {pd[name]}", file=sys.stderr, flush=True)
+    pd["qr_step_speedup"] = pd["dense"]["qr_step_ms"] / pd["structured"]["qr_step_ms"]
+    out = {"metric": "structured vs dense QR of [X; I] (GEQRF, ORGQR) and the QR-type step", "n_gpus": 1,
+           "steps": args.steps, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "X Gaussian m x n, m = n; M = [X; I] (m + n) x n; Zolo-PD at "
+                                  f"{n}x{n} kappa={kappa:g} r={args.r}"},
+           "qr": rows, "zolo_pd": pd}
+    print(json.dumps(out), flush=True)
+    z.close()
 
 
 def bench_gemm_classes(args):
@@ -141,7 +327,7 @@ def bench_batched(args):
     mats = []
     for sp in specs:
         A = W.svd_matrix(sp["m"], sp["n"], sp["kappa"], sp["seed_u"], sp["seed_v"])[0]
-        mats.append(torch.from_numpy(np.ascontiguousarray(A.T)).to("cuda:0").t())
+        mats.append(zolo.to_device(A))
     ls = [1.0 / sp["kappa"] for sp in specs]
     z = zolo.Zolo()
     for _ in range(args.warmup):
@@ -152,8 +338,7 @@ def bench_batched(args):
         _, _, infos = z.pd_batched(mats, alphas=[1.0] * len(mats), ls=ls, batch_streams=args.batch_streams)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
-    fl = sum(paper_flops(sp["m"], sp["n"], inf["r"], inf["kinds"], 1 if inf["orth_check"] >= 0 else 0)
-             for sp, inf in zip(specs, infos))
+    fl = sum(inf["flops_paper"] for inf in infos)
     # accuracy on a sample of the batch
     errs = []
     for i in range(0, len(mats), max(1, len(mats) // 16)):
@@ -190,7 +375,7 @@ def bench_precision_study(args):
     rows = []
     for kappa in (1e4, 1e8, 1e12):
         sigma = W.logspaced_sigma(n, kappa)
-        A = torch.from_numpy(np.ascontiguousarray(((U * sigma) @ V.T).T)).to("cuda:0").t()
+        A = zolo.to_device((U * sigma) @ V.T)
         row = {"kappa": kappa}
         for prec_name, prec in (("fp64", 0), ("mixed", 1)):
             for _ in range(args.warmup):
@@ -258,11 +443,10 @@ def bench_learned(args):
     cases = []
     for kappa in (1e8, 1e16):
         A = W.svd_matrix(n, n, kappa, 1000 + 3, 2000 + 3)[0]
-        cases.append((f"log-spaced kappa={kappa:g}", torch.from_numpy(np.ascontiguousarray(A.T)).to("cuda:0").t(),
-                      1.0))
+        cases.append((f"log-spaced kappa={kappa:g}", zolo.to_device(A), 1.0))
     Sp = W.sparse_pattern(n)
     cases.append(("sparse pattern (band 64, 1% off-band)",
-                  torch.from_numpy(np.ascontiguousarray(Sp.T)).to("cuda:0").t(), None))
+                  zolo.to_device(Sp), None))
     rows = []
     for name, A, alpha in cases:
         row = {"matrix": name}
@@ -330,6 +514,15 @@ def main():
                     help="with --batched: HIP hardware queues (GPU_MAX_HW_QUEUES, at most 24; 0: leave as is)")
     ap.add_argument("--gemm-classes", action="store_true",
                     help="instead: time the rank-256 update and the 8192^3 product alone")
+    ap.add_argument("--r-sweep", action="store_true",
+                    help="instead: FP64 solves of the headline matrix for each r in --sweep-r, then r chosen by "
+                         "least predicted time")
+    ap.add_argument("--sweep-r", type=int, nargs="+", default=[1, 2, 3, 4, 5, 6, 7, 8])
+    ap.add_argument("--qr-ablation", action="store_true",
+                    help="instead: structured vs dense QR of [X; I] (Table 2) at --ablation-n, and inside Zolo-PD")
+    ap.add_argument("--ablation-n", type=int, nargs="+", default=[5000, 10000])
+    ap.add_argument("--svd", action="store_true",
+                    help="instead: Zolo-SVD of the n x n generator matrix (use with --n 4096)")
     ap.add_argument("--batched", type=int, default=0,
                     help="instead: Zolo-PD of this many uneven matrices (n in [64,1024], m in [n,2n], "
                          "kappa log-uniform in [1e2,1e12]) in one zolo_pd_batched call")
@@ -356,12 +549,18 @@ def main():
         return bench_precision_study(args)
     if args.learned:
         return bench_learned(args)
+    if args.r_sweep:
+        return bench_r_sweep(args)
+    if args.svd:
+        return bench_svd(args)
+    if args.qr_ablation:
+        return bench_qr_ablation(args)
     n, kappa, r = args.n, args.kappa, args.r
     print(f"[bench] generating {n}x{n} kappa={kappa:g} input", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     A_np, U, sigma, V = W.svd_matrix(n, n, kappa, 1000 + 1, 2000 + 1)
     print(f"[bench] input ready in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
-    A = torch.from_numpy(np.ascontiguousarray(A_np.T)).to("cuda:0").t()   # column-major view
+    A = zolo.to_device(A_np)   # column-major device copy
     z = zolo.Zolo()
     l = 1.0 / kappa
     if args.calibrate_copy_mib > 0:
@@ -389,9 +588,10 @@ def main():
     zolo.stats_enable(False)
     st = zolo.stats()
     info = infos[-1]
-    checks = 1 if info["orth_check"] >= 0 else 0
+    checks = info["checks"]
     kinds = info["kinds"]
-    fl_paper = paper_flops(n, n, r, kinds, checks)
+    fl_paper = info["flops_paper"]           # counts every verified check the solve took
+    assert abs(fl_paper - paper_flops(n, n, r, kinds, checks)) <= 1e-9 * fl_paper
     print(f"[bench] {args.steps} timed steps: {dt * 1e3:.1f} ms/step, schedule {''.join(kinds)}",
           file=sys.stderr, flush=True)
 
@@ -459,6 +659,7 @@ def main():
         "tflops_executed": info["flops_exec"] / dt / 1e12,
         "schedule": "".join(kinds),
         "iters": info["iters"],
+        "verified_checks": checks,
         "stage_ms": {"scale": info["t_stage_ms"][0], "qr_steps": info["t_stage_ms"][1],
                      "chol_steps": info["t_stage_ms"][2], "checks": info["t_stage_ms"][3],
                      "H": info["t_stage_ms"][4]},

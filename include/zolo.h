@@ -70,9 +70,14 @@ typedef struct {
     double tau;          /* verified-stop threshold (default 5e-14) */
     double chol_switch;  /* QR-type step while (1+c_1)/(l^2+c_1) > chol_switch
                             (default 100; the QDWH switch of Section 2.1) */
-    int qr_variant;      /* 0 (default, the only value accepted): structured QR of
-                            [X; sqrt(c) I] with m + NB live rows per panel
-                            (Section 3.1) */
+    int qr_variant;      /* 0 (default): structured QR of [X; sqrt(c) I] with
+                            m + NB live rows per panel (Section 3.1);
+                            1: the same blocked Householder QR and Q formation
+                            applied to [X; sqrt(c) I] as a dense (m + n) x n
+                            matrix (every reflector spans all rows below its
+                            pivot, Q_2 is used as a full matrix), the
+                            comparison of Section 3.1 / Table 2.  Needs the
+                            workspace of an (m + n) x n problem. */
     int precision;       /* 0 (default): every step in FP64.
                             1 mixed: every Cholesky-type step that is not
                             predicted to be the last (l_next < 1 - 1e-15) runs
@@ -107,7 +112,15 @@ typedef struct {
                             hardware queues for their streams
                             (GPU_MAX_HW_QUEUES, 4 unless set; about 16 suits
                             16 solves). */
-    int reserved[7];
+    int r_policy;        /* how r is chosen when the caller passes r <= 0:
+                            0 (default) the smallest r whose scalar recursion
+                            converges within two steps (Section 2.2, Table 1;
+                            with l_source = 1, the network's degree output);
+                            1 the r of least predicted time on this GPU: the
+                            step kinds each r takes from l (the same rules as
+                            the solve) priced by a per-step cost model of the
+                            library's kernels (zolo_predict). */
+    int reserved[6];
 } zolo_opts;
 
 /* Per-call report. */
@@ -120,6 +133,7 @@ typedef struct {
     int l_reestimates;     /* verified stop: times sqrt(n) d >= 1 voided the
                               bound from d (l was above sigma_min) and l was
                               re-estimated from the current X */
+    int checks;            /* verified stop: orthogonality checks computed */
     char kind[ZOLO_MAX_ITER + 1];  /* 'Q' or 'C' per iteration, NUL-terminated */
     char prec[ZOLO_MAX_ITER + 1];  /* 'd' (FP64) or 's' (FP32) per iteration */
     double alpha;          /* scaling alpha >= sigma_max(A) used, X0 = A / alpha */
@@ -161,39 +175,65 @@ int zolo_destroy(zolo_handle handle);
  * Returns 0, -1 if l is not in (0, 1], -2 if r is not in [1, ZOLO_MAX_R]. */
 int zolo_coeffs(double l, int r, double* c, double* a, double* mhat, double* l_next);
 
+/* Predicted schedule and time of a Zolo-PD solve of an m x n matrix from
+ * lower bound l with degree r (host only, no handle, nothing launched).
+ * The step kinds follow the solve's own rules (Algorithm 1 step 4 with the
+ * coefficients of eqs. (7)-(10), QR-type while the bound on kappa(Z_j)
+ * exceeds chol_switch, one verified check once l reaches 1 - 1e-15); each
+ * step is priced by a cost model of this library's kernels on MI355X
+ * (rates of the FP64 matrix-core products and per-panel latencies of the
+ * factorisations).  kinds (may be NULL) receives 'Q'/'C' per step,
+ * NUL-terminated (ZOLO_MAX_ITER + 1 chars); *ms (may be NULL) the predicted
+ * milliseconds including H.  Returns 0, -1 for l outside (0, 1], -2 for r
+ * outside [1, ZOLO_MAX_R], -3/-4 for m < n or n < 1. */
+int zolo_predict(double l, int r, int m, int n, double chol_switch, char* kinds, double* ms);
+
 /* Zolo-PD, Algorithm 1: A (m x n, lda >= m) -> Qp (m x n, ldq >= m) and
  * H (n x n, ldh >= n), with m >= n >= 1.
  *   alpha > 0: used as the upper bound of sigma_max(A) (Algorithm 1 step 1);
  *              alpha <= 0: estimated as 1.01 x a power-iteration estimate.
  *   l in (0,1]: lower bound of sigma_min(A/alpha) (step 2);
  *              l <= 0: estimated as 1/(sqrt(n) ||R^{-1}||_1) from A/alpha = QR.
- *   r in [1,8]: Zolotarev degree; r <= 0: the smallest r whose scalar
- *              recursion converges within two steps (step 3, Table 1).
- * opts may be NULL (defaults).  info may be NULL. */
+ *   r in [1,8]: Zolotarev degree; r <= 0: chosen by opts->r_policy (the
+ *              smallest r whose scalar recursion converges within two
+ *              steps, step 3 and Table 1, by default).
+ * opts may be NULL (defaults).  info may be NULL; when given it is written
+ * on every return, with info->status equal to the return code. */
 int zolo_pd(zolo_handle handle, int m, int n, const double* A, int lda,
             double alpha, double l, int r,
             double* Qp, int ldq, double* H, int ldh,
             const zolo_opts* opts, zolo_info* info);
 
 /* Zolo-PD of `count` independent matrices of possibly different shapes (the
- * paper's per-group work of Algorithm 3 steps 1-4, one matrix at a time on
- * the handle's stream, with the workspace sized once for the largest one).
+ * paper's per-group work of Algorithm 3 steps 1-4).  opts->batch_streams
+ * solves run at once, each on a worker stream of the handle with its own
+ * workspace sized for the largest matrix; the workers are created on the
+ * first such call and kept (workspaces grown on demand) until zolo_destroy.
+ * If fewer workers can be set up than asked for, the call runs on those it
+ * has (ZOLO_ALLOC only when none can be).  With batch_streams = 1 the
+ * matrices are solved one after another on the handle's stream.  The
+ * call waits for the caller's stream before it starts and returns when
+ * every result is complete.
  * Arrays have `count` entries: m, n, lda, ldq, ldh, alpha, l, r are HOST
  * arrays; A, Qp, H are HOST arrays of DEVICE pointers.  alpha, l, r may be
  * NULL (all estimated / chosen by the policy).  info may be NULL or point to
  * `count` structs.  Returns 0 if every matrix converged, 1 if some did not,
  * or the first error code (negative: -(argument index) of the first bad
- * argument, counting a bad entry of an array as that array's index). */
+ * argument, counting a bad entry of an array as that array's index; -14 for
+ * invalid opts). */
 int zolo_pd_batched(zolo_handle handle, int count, const int* m, const int* n,
                     const double* const* A, const int* lda, const double* alpha,
                     const double* l, const int* r, double* const* Qp, const int* ldq,
                     double* const* H, const int* ldh, const zolo_opts* opts, zolo_info* info);
 
 /* Zolo-SVD, Algorithm 2: A = Qp H by zolo_pd, then H = V diag(S) V^T by a
- * plain FP64 symmetric eigensolver on the GPU (cyclic Jacobi), then U = Qp V.
- * U is m x n (ldu >= m), S has n entries (host, descending), V is n x n
- * (ldv >= n).  The eigensolver and the product are timed in info->t_stage[5]
- * and [6], apart from the polar decomposition. */
+ * plain FP64 symmetric eigensolver on the GPU (Householder
+ * tridiagonalisation, divide and conquer, back-transformation; the same as
+ * zolo_dsyevd), then U = Qp V.  U is m x n (ldu >= m), S has n entries
+ * (host, descending), V is n x n (ldv >= n).  The eigensolver and the
+ * product are timed in info->t_stage[5] and [6], apart from the polar
+ * decomposition.  Allocates the eigensolver's workspace (about 5 n^2 + m n
+ * doubles) for the call. */
 int zolo_svd(zolo_handle handle, int m, int n, const double* A, int lda,
              double alpha, double l, int r,
              double* U, int ldu, double* S, double* V, int ldv,

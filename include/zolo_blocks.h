@@ -66,6 +66,16 @@ int zolo_strtri_batched(zolo_handle h, int n, const float* R, int ldr, long long
 int zolo_structured_qr_batched(zolo_handle h, int m, int n, const double* pivots, double* M, int ldm,
                                long long strideM, double* R, int ldr, long long strideR, int batch, int form_q);
 
+/* Eigen-decomposition A = Z diag(w) Z^T of a symmetric n x n matrix (lower
+ * triangle read; A is not modified), the eigensolver of Zolo-SVD
+ * (Algorithm 2: H = V diag(S) V^T): Householder tridiagonalisation, divide
+ * and conquer on the tridiagonal matrix, back-transformation.  w (HOST, n
+ * entries) receives the eigenvalues in descending order, Z (device, ldz >= n)
+ * the matching orthonormal eigenvectors.  Allocates its workspace (about
+ * 4 n^2 doubles) for the call.  Returns 0, a negative argument index, 3 if
+ * the workspace cannot be allocated or 4 for a HIP error. */
+int zolo_dsyevd(zolo_handle h, int n, const double* A, int lda, double* w, double* Z, int ldz);
+
 #ifdef __cplusplus
 }
 #endif

@@ -58,6 +58,14 @@ int zolo_autotune_enable(int on);
  * candidates again.  Returns 0. */
 int zolo_autotune_reset(void);
 
+/* Destroys every HIP event the statistics and the autotuner hold (up to
+ * 16384 for the statistics) after waiting for the pending ones; the recorded
+ * figures are kept and recording can resume (events are created again on
+ * demand).  Call it before the process ends, with no solve running, so that
+ * no library-owned HIP object is left for the runtime's own teardown.
+ * Returns 0. */
+int zolo_release_events(void);
+
 #ifdef __cplusplus
 }
 #endif

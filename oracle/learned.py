@@ -45,9 +45,10 @@ G5  Network (3 layers, 64 hidden, tanh): x = (f - mu) / sd,
     h1 = tanh(W1 x + b1), h2 = tanh(W2 h1 + b2), y = W3 h2 + b3.
     y0 estimates log10(sigma_min / sigma_max) of X0 and y1 the degree r.
 G6  Loss: the batch mean of  w (t0 - y0)^2 + c_r (t1 - y1)^2  with
-    w = 1 - q when y0 > t0 (l over-estimated) and w = q otherwise.  With
-    q = 0.1 an over-estimate costs nine times an under-estimate, so y0 leans
-    low and 10^y0 tends to stay a lower bound (an expectile loss).
+    w = 1 - q when y0 > t0 (l over-estimated) and w = q otherwise (an
+    expectile loss).  The library's training uses q = 0.05, so an
+    over-estimate costs nineteen times an under-estimate, y0 leans low and
+    10^y0 tends to stay a lower bound; q is an argument here (default 0.05).
 G7  Adam (Kingma & Ba, ICLR 2015): m <- b1 m + (1 - b1) g,
     v <- b2 v + (1 - b2) g^2, p <- p - lr (m / (1 - b1^t)) /
     (sqrt(v / (1 - b2^t)) + eps), for the trainable part (W, b) only.
@@ -208,7 +209,7 @@ def forward(p, F):
 
 
 # --- G6 -------------------------------------------------------------------
-def loss(y, T, q=0.1, c_r=0.1):
+def loss(y, T, q=0.05, c_r=0.1):
     """Batch loss and its gradient with respect to y (G6)."""
     y = np.asarray(y, dtype=np.float64)
     T = np.asarray(T, dtype=np.float64)

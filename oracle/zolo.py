@@ -155,7 +155,7 @@ def zolo_pd(A, alpha=None, l=None, r=None, *, stop="verified", tau=5e-14,
         r = zc.choose_r(l)
     info = {"status": 1, "iters": 0, "kinds": [], "ls": [], "r": int(r),
             "alpha": float(alpha), "l0": l0, "chol_fallbacks": 0, "l_reestimates": 0,
-            "iterates": [X.copy()] if record else None, "orth_checks": []}
+            "iterates": [X.copy()] if record else None, "orth_checks": [], "check_iters": []}
     for _ in range(max_iter):
         co = zc.coefficients(l, r)
         kind = step_kind(l, co["c"], chol_switch)
@@ -184,6 +184,7 @@ def zolo_pd(A, alpha=None, l=None, r=None, *, stop="verified", tau=5e-14,
             if l_pred >= zc.CONVERGED:
                 d = orthogonality(X)
                 info["orth_checks"].append(d)
+                info["check_iters"].append(info["iters"] - 1)
                 if d <= tau:
                     info["status"] = 0
                     break

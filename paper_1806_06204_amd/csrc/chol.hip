@@ -223,7 +223,7 @@ __global__ __launch_bounds__(256) void trtri_diag_kernel(int n, const T* R, long
 template <class T>
 hipError_t potrf_batched(int n, T* Z, long long ldz, long long sz, int batch, int* info_dev, T* work,
                          hipStream_t st) {
-    hipError_t e = hipMemsetAsync(info_dev, 0, sizeof(int) * batch, st);
+    hipError_t e = zero_ints(info_dev, batch, st);
     if (e != hipSuccess) return e;
     for (int k0 = 0; k0 < n; k0 += kBand) {
         const int band = n - k0 < kBand ? n - k0 : kBand;

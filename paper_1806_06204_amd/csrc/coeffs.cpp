@@ -139,4 +139,74 @@ int choose_r(double l) {
     return kMaxR;
 }
 
+int predict_kinds(double l, int r, double chol_switch, char* kinds, int max_steps) {
+    Coeffs co;
+    int k = 0;
+    while (k < max_steps) {
+        if (compute_coeffs(l, r, &co) != 0) break;
+        kinds[k++] = co.kappa_z > chol_switch ? 'Q' : 'C';
+        l = co.l_next;
+        if (l >= kConverged) break;
+    }
+    kinds[k] = 0;
+    return k;
+}
+
+// Cost model of one solve on one MI355X, fitted to solves of this library
+// (n = 8192: the QR-type step of degree 8 takes 596 ms of which the
+// 64-column panels take 75 ms, a Cholesky-type step 144 ms; the sweep over
+// r of the same matrix sets the panel and small-r terms).  The matrix-core
+// products run at kRate once they fill the chip; below kFill flops per
+// launch the rate falls in proportion (launch latency and too few tiles).
+namespace {
+constexpr double kRate = 42.0e9;          // flops per ms of the products of a step
+constexpr double kRateBig = 52.0e9;       // flops per ms of X^T X and Qp^T A
+constexpr double kFill = 2.0e10;          // flops of a product that fills the chip
+constexpr double kPanel0 = 0.30;          // ms per 64-column panel, fixed part
+constexpr double kPanelRow = 0.036 / 8256; // ms per panel per live row and matrix
+constexpr double kLaunch = 0.012;         // ms per dependent launch
+
+double gemm_ms(double flops, double rate, double launches) {
+    const double eff = flops / (flops + kFill / 8.0);
+    return flops / (rate * eff) + launches * kLaunch;
+}
+}  // namespace
+
+double predict_ms(double l, int r, int m, int n, double chol_switch, char* kinds) {
+    char buf[64];
+    char* kk = kinds ? kinds : buf;
+    const int steps = predict_kinds(l, r, chol_switch, kk, 16);
+    const double M = m, N = n, panels = (n + 63) / 64;
+    double ms = 0.0;
+    for (int s = 0; s < steps; ++s) {
+        if (kk[s] == 'Q') {
+            // GEQRF + ORGQR (2 M N^2 each) and the combination (M N^2) per j;
+            // 128 panels of m + 64 live rows each way, about 12 launches per
+            // 256-column superblock.
+            ms += gemm_ms(5.0 * r * M * N * N, kRate, 12.0 * panels / 4.0);
+            ms += panels * (kPanel0 + kPanelRow * r * (M + 64.0));
+        } else {
+            // X^T X, r POTRF/TRTRI (N^3 / 3 each) and the F accumulation
+            // (N^3 / 3 per j), X F; about 6 launches per 64 columns.
+            ms += gemm_ms(3.0 * M * N * N + r * N * N * N, kRate, 6.0 * panels);
+        }
+    }
+    ms += gemm_ms(M * N * N, kRateBig, 2.0);        // the verified check
+    ms += gemm_ms(2.0 * M * N * N, kRateBig, 2.0);  // H
+    return ms;
+}
+
+int choose_r_time(double l, int m, int n, double chol_switch) {
+    int best = 1;
+    double best_ms = 0.0;
+    for (int r = 1; r <= kMaxR; ++r) {
+        const double t = predict_ms(l, r, m, n, chol_switch, nullptr);
+        if (r == 1 || t < best_ms) {
+            best = r;
+            best_ms = t;
+        }
+    }
+    return best;
+}
+
 }  // namespace zolo

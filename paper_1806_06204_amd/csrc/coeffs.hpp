@@ -26,4 +26,14 @@ int iterations_to_converge(double l0, int r, int max_iter);
 // Smallest r <= 8 converging in at most two iterations from l.
 int choose_r(double l);
 
+// Step kinds ('Q'/'C', NUL-terminated, at most max_steps) the solve takes
+// from l with degree r, assuming the verified check passes once l reaches
+// 1 - 1e-15.  Returns the number of steps.
+int predict_kinds(double l, int r, double chol_switch, char* kinds, int max_steps);
+// Predicted milliseconds of a solve of m x n with degree r from l on one
+// MI355X (cost model of the library's kernels; see coeffs.cpp).
+double predict_ms(double l, int r, int m, int n, double chol_switch, char* kinds);
+// r in [1, 8] with the least predicted_ms (ties: the smaller r).
+int choose_r_time(double l, int m, int n, double chol_switch);
+
 }  // namespace zolo

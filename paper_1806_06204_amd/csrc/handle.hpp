@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <vector>
 
 struct zolo_handle_s {
     hipStream_t stream = nullptr;
@@ -22,4 +23,10 @@ struct zolo_handle_s {
     // Solves of zolo_pd_batched (sequential or concurrent alike, so that
     // both give the same bits): panels of few rows take one workgroup.
     bool single_panels = false;
+    // zolo_pd_batched's workers, created on its first call with several
+    // streams and kept (streams, pinned buffers, events, workspaces grown on
+    // demand) until zolo_destroy; the shared stream of their cooperative
+    // panels.
+    std::vector<zolo_handle_s*> workers;
+    hipStream_t worker_panel_stream = nullptr;
 };

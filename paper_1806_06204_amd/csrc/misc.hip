@@ -334,6 +334,18 @@ hipError_t power_step(int m, int n, const double* A, long long lda, double* v, d
     return hipGetLastError();
 }
 
+__global__ void zero_ints_kernel(int* p, int count) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+hipError_t zero_ints(int* p, int count, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    int grid = (count + kThreads - 1) / kThreads;
+    if (grid > 1024) grid = 1024;
+    zero_ints_kernel<<<grid, kThreads, 0, st>>>(p, count);
+    return hipGetLastError();
+}
+
 hipError_t fill_vector(int n, double* v, double val, hipStream_t st) {
     fill_vec_kernel<<<(n + kThreads - 1) / kThreads, kThreads, 0, st>>>(n, v, val);
     return hipGetLastError();

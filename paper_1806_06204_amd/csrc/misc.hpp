@@ -41,6 +41,8 @@ hipError_t orth2(int n, const double* G, long long ldg, double* part, double* ou
 hipError_t power_step(int m, int n, const double* A, long long lda, double* v, double* u, double* w, double* lam,
                       hipStream_t st);
 hipError_t fill_vector(int n, double* v, double val, hipStream_t st);
+// p[0..count) = 0 by a kernel (not a memset node, so that it may be captured).
+hipError_t zero_ints(int* p, int count, hipStream_t st);
 // *out = max_j sum_{i<=j} |R[i][j]|  (colsum: n doubles scratch).
 hipError_t norm1_upper(int n, const double* R, long long ldr, double* colsum, double* out, hipStream_t st);
 

@@ -427,16 +427,8 @@ struct Geometry {
     bool lds;
 };
 
-// Rows each workgroup owns when the slab stays in global memory
-// (ZOLO_PANEL_ROWS overrides; default 256).
-int panel_rows_target() {
-    static int v = [] {
-        const char* e = getenv("ZOLO_PANEL_ROWS");
-        int x = e ? atoi(e) : 0;
-        return x >= 64 && x <= 8192 ? x : 256;
-    }();
-    return v;
-}
+// Rows each workgroup owns when the slab stays in global memory.
+constexpr int kPanelRowsTarget = 256;
 
 // Panels of the solves of zolo_pd_batched with at most this many live rows
 // take one workgroup per matrix: an ordinary launch on the solve's own
@@ -512,7 +504,7 @@ Geometry panel_geometry(int L, int batch) {
             }
         }
     }
-    const int target = panel_rows_target();
+    const int target = kPanelRowsTarget;
     int G = (L + target - 1) / target;
     if (G < 1) G = 1;
     int cap = global_coresident() / batch;
@@ -733,7 +725,7 @@ hipError_t structured_geqrf(int m, int e, int n, double* M, long long ld, long l
     const long long stT = (long long)npanels * kNB * kNB;
     const long long stb = (long long)nblocks * kQrBlock * kQrBlock;
     const long long sts = (long long)nsuper * kQrSuper * kQrSuper;
-    hipError_t err = hipMemsetAsync(w.flags, 0, sizeof(unsigned) * w.flag_elems, st);
+    hipError_t err = zero_ints(reinterpret_cast<int*>(w.flags), (int)w.flag_elems, st);
     if (err != hipSuccess) return err;
     for (int Q = 0; Q < nsuper; ++Q) {
         const int s0 = Q * kQrSuper;

@@ -114,6 +114,21 @@ int zolo_stats_reset(void) {
     return 0;
 }
 
+int zolo_release_events(void) {
+    zolo::Registry& r = zolo::reg();
+    {
+        std::lock_guard<std::mutex> lock(r.mu);
+        r.collect();
+        for (size_t i = 0; i < r.ev0.size(); ++i) {
+            (void)hipEventDestroy(r.ev0[i]);
+            (void)hipEventDestroy(r.ev1[i]);
+        }
+        r.ev0.clear();
+        r.ev1.clear();
+    }
+    return zolo_autotune_reset();
+}
+
 int zolo_stats_count(void) {
     zolo::Registry& r = zolo::reg();
     std::lock_guard<std::mutex> lock(r.mu);

@@ -19,14 +19,10 @@ import numpy as np
 
 
 def haar(m, k, seed):
-    """m x k matrix with orthonormal columns, Haar distributed (seeded).
-
-    The Gaussian matrix comes from NumPy's seeded generator; its QR is taken
-    with PyTorch's CPU LAPACK (several times faster than NumPy's at n = 8192)."""
-    import torch
+    """m x k matrix with orthonormal columns, Haar distributed (seeded): the
+    Gaussian matrix from NumPy's seeded generator, its QR by NumPy's LAPACK."""
     g = np.random.default_rng(seed).standard_normal((m, k))
-    q, r = torch.linalg.qr(torch.from_numpy(g))
-    q, r = q.numpy(), r.numpy()
+    q, r = np.linalg.qr(g)
     d = np.sign(np.diag(r))
     d[d == 0] = 1.0
     return q * d

@@ -11,8 +11,10 @@ Stacks of matrices for the batched building blocks are tensors of shape
 (batch, m, n) and are handled the same way per matrix.
 """
 
+import atexit
 import ctypes
 import os
+import weakref
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libzolo.so")
@@ -26,12 +28,12 @@ STATUS = {0: "ok", 1: "not converged", 2: "non-finite input", 3: "allocation fai
 class ZoloOpts(ctypes.Structure):
     _fields_ = [("max_iter", c_int), ("stop_rule", c_int), ("tau", c_double), ("chol_switch", c_double),
                 ("qr_variant", c_int), ("precision", c_int), ("compute_errors", c_int), ("l_source", c_int),
-                ("batch_streams", c_int), ("reserved", c_int * 7)]
+                ("batch_streams", c_int), ("r_policy", c_int), ("reserved", c_int * 6)]
 
 
 class ZoloInfo(ctypes.Structure):
     _fields_ = [("status", c_int), ("iters", c_int), ("r_used", c_int), ("chol_fallbacks", c_int), ("l_from", c_int),
-                ("l_reestimates", c_int),
+                ("l_reestimates", c_int), ("checks", c_int),
                 ("kind", ctypes.c_char * (MAX_ITER + 1)), ("prec", ctypes.c_char * (MAX_ITER + 1)),
                 ("alpha", c_double), ("l0", c_double),
                 ("l_seq", c_double * MAX_ITER), ("orth_check", c_double), ("t_stage", c_double * 8),
@@ -42,7 +44,7 @@ class ZoloInfo(ctypes.Structure):
         it = self.iters
         return {"status": self.status, "iters": it, "r": self.r_used, "chol_fallbacks": self.chol_fallbacks,
                 "l_from": ("given", "condition estimate", "learned")[self.l_from],
-                "l_reestimates": self.l_reestimates,
+                "l_reestimates": self.l_reestimates, "checks": self.checks,
                 "kinds": list(self.kind.decode()), "prec": self.prec.decode(), "alpha": self.alpha,
                 "l0": self.l0,
                 "ls": list(self.l_seq[:it]), "orth_check": self.orth_check,
@@ -59,7 +61,7 @@ EXPORTS = ["zolo_default_opts", "zolo_create", "zolo_set_stream", "zolo_destroy"
            "zolo_autotune_enable", "zolo_autotune_reset",
            "zolo_sketch_features", "zolo_surrogate_features", "zolo_mlp_stats", "zolo_mlp_work_elems",
            "zolo_mlp_forward", "zolo_mlp_loss", "zolo_mlp_backward", "zolo_mlp_adam", "zolo_mlp_train",
-           "zolo_set_estimator", "zolo_choose_r"]
+           "zolo_set_estimator", "zolo_choose_r", "zolo_predict", "zolo_release_events", "zolo_dsyevd"]
 NF, MLP_NPARAMS, MLP_NSTATS = 39, 6928, 78
 
 
@@ -82,6 +84,7 @@ def load():
     lib.zolo_coeffs.argtypes = [c_double, c_int, D, D, D, D]
     lib.zolo_pd.argtypes = [P, c_int, c_int, P, c_int, c_double, c_double, c_int, P, c_int, P, c_int,
                             ctypes.POINTER(ZoloOpts), ctypes.POINTER(ZoloInfo)]
+    lib.zolo_dsyevd.argtypes = [P, c_int, P, c_int, D, P, c_int]
     PP = ctypes.POINTER(c_void_p)
     IP = ctypes.POINTER(c_int)
     lib.zolo_pd_batched.argtypes = [P, c_int, IP, IP, PP, IP, D, D, IP, PP, IP, PP, IP,
@@ -117,6 +120,8 @@ def load():
     lib.zolo_mlp_train.argtypes = [P, c_int, c_int, c_int, P, P, P, P, P, P, c_int, F, F, F, P, P, P]
     lib.zolo_set_estimator.argtypes = [P, P, c_int]
     lib.zolo_choose_r.argtypes = [c_double]
+    lib.zolo_predict.argtypes = [c_double, c_int, c_int, c_int, c_double, ctypes.c_char_p, D]
+    lib.zolo_release_events.argtypes = []
     for name in EXPORTS:
         if name not in ("zolo_default_opts",):
             getattr(lib, name).restype = c_int
@@ -136,6 +141,32 @@ def coeffs(l, r):
     if rc != 0:
         raise ValueError(f"zolo_coeffs rejected l={l}, r={r} (code {rc})")
     return {"c": list(c), "a": list(a), "mhat": mh.value, "l_next": ln.value}
+
+
+def predict(l, r, m, n, chol_switch=100.0):
+    """The library's predicted schedule and milliseconds of a solve (host
+    only): (kinds string, ms)."""
+    kinds = ctypes.create_string_buffer(MAX_ITER + 1)
+    ms = c_double()
+    rc = load().zolo_predict(float(l), int(r), int(m), int(n), float(chol_switch), kinds, ctypes.byref(ms))
+    if rc != 0:
+        raise ValueError(f"zolo_predict rejected l={l}, r={r}, m={m}, n={n} (code {rc})")
+    return kinds.value.decode(), ms.value
+
+
+_live = []
+
+
+def shutdown():
+    """Close every open handle and release the library's HIP events.  Runs
+    at interpreter exit (atexit), before the HIP runtime's own teardown."""
+    for ref in list(_live):
+        z = ref()
+        if z is not None:
+            z.close()
+    _live.clear()
+    if _lib is not None:
+        _lib.zolo_release_events()
 
 
 def stats_enable(on=True):
@@ -177,6 +208,19 @@ def _torch():
     return torch
 
 
+def to_device(A, device="cuda:0"):
+    """A host (m, n) float64 array -> a device tensor of shape (m, n) whose
+    memory is column-major (leading dimension m), copied into one device
+    buffer that the returned view keeps alive."""
+    torch = _torch()
+    import numpy as np
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    buf = torch.empty(m * n, dtype=torch.float64, device=device)
+    buf.copy_(torch.from_numpy(np.asfortranarray(A).reshape(-1, order="F")))
+    return buf.as_strided((m, n), (1, m))
+
+
 def _colmajor(A):
     """(tensor whose memory is A column-major, leading dimension)."""
     if A.dim() == 2 and A.stride(0) == 1 and A.stride(1) >= max(1, A.shape[0]):
@@ -214,9 +258,13 @@ class Zolo:
         if rc != 0:
             _raise(rc, "zolo_create")
         self.h = h
+        _live.append(weakref.ref(self))
 
     def close(self):
+        """Wait for the handle's stream, then release the handle and its
+        workspace (deterministic; also called by shutdown() at exit)."""
         if getattr(self, "h", None):
+            self.stream.synchronize()
             self.lib.zolo_destroy(self.h)
             self.h = None
 
@@ -231,7 +279,7 @@ class Zolo:
         o = ZoloOpts()
         load().zolo_default_opts(ctypes.byref(o))
         names = {"max_iter", "stop_rule", "tau", "chol_switch", "qr_variant", "precision", "compute_errors",
-                 "l_source", "batch_streams"}
+                 "l_source", "batch_streams", "r_policy"}
         for k, v in kw.items():
             if k not in names:
                 raise TypeError(f"unknown option {k}")
@@ -241,6 +289,10 @@ class Zolo:
                 v = {"condest": 0, "learned": 1}[v]
             if k == "precision" and isinstance(v, str):
                 v = {"fp64": 0, "mixed": 1}[v]
+            if k == "r_policy" and isinstance(v, str):
+                v = {"two-step": 0, "time": 1}[v]
+            if k == "qr_variant" and isinstance(v, str):
+                v = {"structured": 0, "dense": 1}[v]
             setattr(o, k, v)
         return o
 
@@ -255,10 +307,10 @@ class Zolo:
         o = self.options(**opts)
         info = ZoloInfo()
         rc = self.lib.zolo_pd(self.h, m, n, c_void_p(Ac.data_ptr()), lda,
-                              float(alpha) if alpha is not None else 0.0,
-                              float(l) if l is not None else 0.0, int(r) if r is not None else 0,
-                              c_void_p(Qbuf.data_ptr()), m, c_void_p(Hbuf.data_ptr()), n,
-                              ctypes.byref(o), ctypes.byref(info))
+                float(alpha) if alpha is not None else 0.0,
+                float(l) if l is not None else 0.0, int(r) if r is not None else 0,
+                c_void_p(Qbuf.data_ptr()), m, c_void_p(Hbuf.data_ptr()), n,
+                ctypes.byref(o), ctypes.byref(info))
         if check and rc not in (0, 1):
             _raise(rc, "zolo_pd")
         return Qbuf.t(), Hbuf.t(), info.as_dict()
@@ -370,6 +422,22 @@ class Zolo:
         if rc:
             _raise(rc, f"zolo_{p}trtri_batched")
         return Ib.transpose(-1, -2)
+
+    def syevd(self, A):
+        """Symmetric eigen-decomposition of an (n, n) float64 device tensor
+        (lower triangle read): (w numpy descending, Z device (n, n))."""
+        torch = _torch()
+        import numpy as np
+        _check_tensor(A, "A")
+        n = A.shape[0]
+        Ac, lda = _colmajor(A)
+        Zbuf = torch.empty((n, n), dtype=torch.float64, device=A.device)
+        w = np.zeros(n)
+        rc = self.lib.zolo_dsyevd(self.h, n, c_void_p(Ac.data_ptr()), lda, w.ctypes.data_as(ctypes.POINTER(c_double)),
+                                  c_void_p(Zbuf.data_ptr()), n)
+        if rc:
+            _raise(rc, "zolo_dsyevd")
+        return w, Zbuf.t()
 
     # -- learned l/r estimator (zolo_learn.h) -------------------------------
     def sketch_features(self, X0, seed):
@@ -500,3 +568,6 @@ class Zolo:
 def choose_r(l):
     """The library's degree policy (host only)."""
     return int(load().zolo_choose_r(float(l)))
+
+
+atexit.register(shutdown)

@@ -99,3 +99,54 @@ def test_autotune_switch_is_host_only(lib):
     assert lib.zolo_autotune_reset() == 0
     assert lib.zolo_autotune_enable(0) == 0
     assert lib.zolo_autotune_reset() == 0
+
+
+def _oracle_kinds(l, r, chol_switch=100.0):
+    from oracle import zolo as oz
+    kinds = []
+    while len(kinds) < 16:
+        co = oc.coefficients(l, r)
+        kinds.append(oz.step_kind(l, co["c"], chol_switch))
+        l = co["l_next"]
+        if l >= oc.CONVERGED:
+            break
+    return "".join(kinds)
+
+
+def test_predicted_schedule_matches_oracle_rules(lib):
+    # zolo_predict follows the solve's own step rules (R6 step kind, the
+    # l-update of eqs. (7)-(10)); the schedules equal the oracle's scalar
+    # recursion (no verified re-estimate happens when l is exact).
+    from paper_1806_06204_amd import zolo
+    for l in [1e-16, 1e-12, 1e-8, 1e-4, 0.1, 0.9]:
+        for r in range(1, 9):
+            kinds, ms = zolo.predict(l, r, 8192, 8192)
+            assert kinds == _oracle_kinds(l, r), (l, r)
+            assert ms > 0.0
+    # QDWH (r = 1) at kappa = 1e16 takes two QR-type and four Cholesky-type steps.
+    assert zolo.predict(1e-16, 1, 8192, 8192)[0] == "QQCCCC"
+    with pytest.raises(ValueError):
+        zolo.predict(0.0, 3, 10, 10)
+    with pytest.raises(ValueError):
+        zolo.predict(0.5, 9, 10, 10)
+    with pytest.raises(ValueError):
+        zolo.predict(0.5, 3, 5, 10)
+
+
+def test_predicted_time_grows_with_work(lib):
+    # The cost model prices flops: more columns, more rows or another step
+    # never make a solve cheaper.
+    from paper_1806_06204_amd import zolo
+    for r in (1, 3, 8):
+        t1 = zolo.predict(1e-8, r, 2048, 1024)[1]
+        t2 = zolo.predict(1e-8, r, 4096, 1024)[1]
+        t3 = zolo.predict(1e-8, r, 4096, 2048)[1]
+        assert t1 < t2 < t3
+    assert zolo.predict(1e-16, 3, 4096, 4096)[1] >= zolo.predict(1e-4, 3, 4096, 4096)[1]
+
+
+def test_release_events_is_host_only(lib):
+    # With no statistics or autotuner events alive, releasing them touches
+    # no device; recording can start again afterwards.
+    assert lib.zolo_release_events() == 0
+    assert lib.zolo_release_events() == 0

@@ -130,3 +130,76 @@ def test_predict_clamps_and_layout():
     P["b3"][:] = [-6.0, 4.4]
     l, r = L.predict(p, np.zeros(L.NF))
     assert l == pytest.approx(1e-6) and r == 4
+
+
+def _random_params(seed):
+    rng = np.random.default_rng(seed)
+    p = L.init_params(seed + 1, mu=rng.standard_normal(L.NF), sd=rng.uniform(0.3, 3.0, L.NF))
+    P = L.unpack(p)
+    for b in ("b1", "b2", "b3"):
+        P[b][:] = rng.uniform(-0.5, 0.5, P[b].shape)
+    return p
+
+
+def test_forward_matches_torch_modules_in_float64():
+    # G5 against an independent implementation: torch.nn.Linear / tanh layers
+    # in float64 holding the same weights (nn.Linear computes x W^T + b with W
+    # of shape (out, in), the layout W1[o][i] of the flat vector).
+    import torch
+    p = _random_params(40)
+    P = L.unpack(p)
+    F = np.random.default_rng(41).standard_normal((7, L.NF)) * 3.0
+    net = torch.nn.Sequential(torch.nn.Linear(L.NF, L.NH), torch.nn.Tanh(), torch.nn.Linear(L.NH, L.NH),
+                              torch.nn.Tanh(), torch.nn.Linear(L.NH, L.NO)).double()
+    with torch.no_grad():
+        for lin, w, b in ((net[0], "W1", "b1"), (net[2], "W2", "b2"), (net[4], "W3", "b3")):
+            lin.weight.copy_(torch.from_numpy(P[w].copy()))
+            lin.bias.copy_(torch.from_numpy(P[b].copy()))
+        x = (torch.from_numpy(F) - torch.from_numpy(P["mu"].copy())) / torch.from_numpy(P["sd"].copy())
+        ref = net(x).numpy()
+    y, cache = L.forward(p, F)
+    assert np.abs(y - ref).max() <= 1e-14 * max(1.0, np.abs(ref).max())
+    assert np.abs(cache["x"] - x.numpy()).max() == 0.0
+
+
+def test_forward_hand_worked_example():
+    # One path through the network, worked out by hand: x0 = (f0 - mu0)/sd0
+    # = (1.5 - 0.5)/0.5 = 2; h1_0 = tanh(1 * 2 + 0.5); every other h1 is
+    # tanh(0) = 0; h2_1 = tanh(2 h1_0 - 0.25), h2_0 = tanh(-0.25);
+    # y0 = 3 h2_1 + 0.25, y1 = -h2_0 + 4.  Dividing by sd the other way,
+    # dropping a bias or transposing W2 or W3 (off-diagonal entries) changes
+    # the numbers.
+    p = np.zeros(L.N_PARAMS)
+    P = L.unpack(p)
+    P["mu"][:] = 0.0
+    P["sd"][:] = 1.0
+    P["mu"][0], P["sd"][0] = 0.5, 0.5
+    P["W1"][0, 0] = 1.0
+    P["b1"][0] = 0.5
+    P["W2"][1, 0] = 2.0
+    P["b2"][:2] = -0.25
+    P["W3"][0, 1] = 3.0
+    P["W3"][1, 0] = -1.0
+    P["b3"][:] = [0.25, 4.0]
+    f = np.zeros(L.NF)
+    f[0] = 1.5
+    f[5] = 7.0            # W1[:, 5] = 0: no influence
+    y, _ = L.forward(p, f[None, :])
+    h1 = math.tanh(2.5)
+    assert y[0, 0] == pytest.approx(3.0 * math.tanh(2.0 * h1 - 0.25) + 0.25, abs=1e-15)
+    assert y[0, 1] == pytest.approx(-math.tanh(-0.25) + 4.0, abs=1e-15)
+
+
+def test_standardize_stats_closed_forms():
+    # Population statistics (divide by the number of samples, not one less)
+    # with sd floored at 1e-6 for a constant feature.
+    F = np.array([[0.0, 2.0, 5.0], [2.0, 2.0, 1.0], [4.0, 2.0, 3.0], [6.0, 2.0, 7.0]])
+    mu, sd = L.standardize_stats(F)
+    assert np.array_equal(mu, [3.0, 2.0, 4.0])
+    assert sd[0] == pytest.approx(math.sqrt(5.0), abs=1e-15)    # (9+1+1+9)/4
+    assert sd[1] == 1e-6
+    assert sd[2] == pytest.approx(math.sqrt(5.0), abs=1e-15)    # (1+9+1+9)/4
+    # Standardised features then have mean 0 and population variance 1.
+    X = (F[:, [0, 2]] - mu[[0, 2]]) / sd[[0, 2]]
+    assert np.abs(X.mean(axis=0)).max() == 0.0
+    assert np.allclose((X * X).mean(axis=0), 1.0, rtol=1e-15)
