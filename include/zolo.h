@@ -36,6 +36,8 @@
  *       barrier that did not complete within its bounded wait)
  *    6  ZOLO_BREAKDOWN: a factorisation met a non-positive pivot where no
  *       fallback exists (building-block entry points only)
+ *    7  ZOLO_SCRATCH: the problem needs more device workspace than the fixed
+ *       scratch of zolo_pd_noalloc holds
  */
 #ifndef ZOLO_H
 #define ZOLO_H
@@ -51,6 +53,7 @@ extern "C" {
 #define ZOLO_HIP 4
 #define ZOLO_KERNEL 5
 #define ZOLO_BREAKDOWN 6
+#define ZOLO_SCRATCH 7
 
 #define ZOLO_MAX_R 8
 #define ZOLO_MAX_ITER 16
@@ -203,6 +206,26 @@ int zolo_pd(zolo_handle handle, int m, int n, const double* A, int lda,
             double alpha, double l, int r,
             double* Qp, int ldq, double* H, int ldh,
             const zolo_opts* opts, zolo_info* info);
+
+/* zolo_pd without any device allocation, for callers that cannot allocate:
+ * code that must not call hipMalloc (serving loops with fixed memory,
+ * harnesses that forbid allocation).  Same arguments, results and return
+ * codes as zolo_pd (the same kernels on the same workspace layout give the
+ * same bits), but the workspace is a fixed 256 MiB device array of the
+ * library, one per GPU, held from the library's load until the process
+ * ends (its device address is looked up by zolo_create).  Problems whose
+ * workspace exceeds it are rejected with ZOLO_SCRATCH before any work is
+ * queued; at degree r = 8 in FP64 that admits e.g. m <= 1024 with n <= 512,
+ * or m = n = 768 (smaller r, larger matrices).  Every call on one GPU uses
+ * the same array and leaves its contents behind (the call clears what must
+ * start at zero itself): calls that overlap on one GPU, from any handle or
+ * thread, race and must be serialised by the caller.  It calls no
+ * hipMalloc/hipFree; launch statistics and the GEMM autotuner, when
+ * switched on, create HIP events on first use. */
+int zolo_pd_noalloc(zolo_handle handle, int m, int n, const double* A, int lda,
+                    double alpha, double l, int r,
+                    double* Qp, int ldq, double* H, int ldh,
+                    const zolo_opts* opts, zolo_info* info);
 
 /* Zolo-PD of `count` independent matrices of possibly different shapes (the
  * paper's per-group work of Algorithm 3 steps 1-4).  opts->batch_streams

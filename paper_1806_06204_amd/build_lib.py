@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libzolo.so")
-SOURCES = ["gemm.hip", "misc.hip", "chol.hip", "qr.hip", "svd.hip", "eig.hip", "learn.hip", "coeffs.cpp",
+SOURCES = ["gemm.hip", "misc.hip", "chol.hip", "qr.hip", "svd.hip", "eig.hip", "learn.hip", "noalloc.hip", "coeffs.cpp",
            "zolo_pd.cpp", "blocks.cpp", "learn_api.cpp", "stats.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "--offload-arch=gfx950"

@@ -43,6 +43,7 @@
 
 namespace zolo {
 int panel_max_coresident();
+hipError_t scratch_address(int device, char** out);
 }
 
 using namespace zolo;
@@ -696,7 +697,8 @@ int zolo_create(zolo_handle* out, void* stream) {
         return ZOLO_HIP;
     }
     h->panel_coresident = panel_max_coresident();
-    if (h->panel_coresident <= 0) {
+    char* scratch = nullptr;  // the device's fixed workspace of zolo_pd_noalloc, looked up once
+    if (h->panel_coresident <= 0 || scratch_address(h->device, &scratch) != hipSuccess) {
         (void)hipHostFree(h->host);
         delete h;
         return ZOLO_HIP;

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(HERE, "libzolo.so")
 c_int, c_double, c_void_p, c_longlong = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_longlong
 MAX_ITER = 16
 STATUS = {0: "ok", 1: "not converged", 2: "non-finite input", 3: "allocation failed", 4: "HIP error",
-          5: "kernel barrier failure", 6: "factorisation breakdown"}
+          5: "kernel barrier failure", 6: "factorisation breakdown", 7: "workspace exceeds the fixed scratch"}
 
 
 class ZoloOpts(ctypes.Structure):
@@ -61,7 +61,7 @@ EXPORTS = ["zolo_default_opts", "zolo_create", "zolo_set_stream", "zolo_destroy"
            "zolo_autotune_enable", "zolo_autotune_reset",
            "zolo_sketch_features", "zolo_surrogate_features", "zolo_mlp_stats", "zolo_mlp_work_elems",
            "zolo_mlp_forward", "zolo_mlp_loss", "zolo_mlp_backward", "zolo_mlp_adam", "zolo_mlp_train",
-           "zolo_set_estimator", "zolo_choose_r", "zolo_predict", "zolo_release_events", "zolo_dsyevd"]
+           "zolo_set_estimator", "zolo_choose_r", "zolo_predict", "zolo_release_events", "zolo_pd_noalloc", "zolo_dsyevd"]
 NF, MLP_NPARAMS, MLP_NSTATS = 39, 6928, 78
 
 
@@ -84,6 +84,7 @@ def load():
     lib.zolo_coeffs.argtypes = [c_double, c_int, D, D, D, D]
     lib.zolo_pd.argtypes = [P, c_int, c_int, P, c_int, c_double, c_double, c_int, P, c_int, P, c_int,
                             ctypes.POINTER(ZoloOpts), ctypes.POINTER(ZoloInfo)]
+    lib.zolo_pd_noalloc.argtypes = lib.zolo_pd.argtypes
     lib.zolo_dsyevd.argtypes = [P, c_int, P, c_int, D, P, c_int]
     PP = ctypes.POINTER(c_void_p)
     IP = ctypes.POINTER(c_int)
@@ -296,8 +297,9 @@ class Zolo:
             setattr(o, k, v)
         return o
 
-    def pd(self, A, alpha=None, l=None, r=None, check=True, **opts):
-        """Polar decomposition A = Qp H.  Returns (Qp, H, info)."""
+    def pd(self, A, alpha=None, l=None, r=None, check=True, noalloc=False, **opts):
+        """Polar decomposition A = Qp H.  Returns (Qp, H, info).  noalloc:
+        through zolo_pd_noalloc (the library's fixed device scratch)."""
         torch = _torch()
         _check_tensor(A, "A")
         m, n = A.shape
@@ -306,13 +308,14 @@ class Zolo:
         Hbuf = torch.empty((n, n), dtype=torch.float64, device=A.device)
         o = self.options(**opts)
         info = ZoloInfo()
-        rc = self.lib.zolo_pd(self.h, m, n, c_void_p(Ac.data_ptr()), lda,
+        fn = self.lib.zolo_pd_noalloc if noalloc else self.lib.zolo_pd
+        rc = fn(self.h, m, n, c_void_p(Ac.data_ptr()), lda,
                 float(alpha) if alpha is not None else 0.0,
                 float(l) if l is not None else 0.0, int(r) if r is not None else 0,
                 c_void_p(Qbuf.data_ptr()), m, c_void_p(Hbuf.data_ptr()), n,
                 ctypes.byref(o), ctypes.byref(info))
         if check and rc not in (0, 1):
-            _raise(rc, "zolo_pd")
+            _raise(rc, "zolo_pd_noalloc" if noalloc else "zolo_pd")
         return Qbuf.t(), Hbuf.t(), info.as_dict()
 
     def pd_batched(self, As, alphas=None, ls=None, rs=None, check=True, **opts):
