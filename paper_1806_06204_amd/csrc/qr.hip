@@ -491,12 +491,23 @@ int global_coresident() {
     return v;
 }
 
+// At most this many workgroups share one matrix's panel: every column's
+// exchange polls and sums one partial per workgroup, so beyond this the
+// exchange costs more than the shorter sweep saves.  Measured on gfx950 for
+// one 8256-row panel per launch (QR-type steps of degree 1 at n = 8192):
+// 129 workgroups (the co-residency limit) 0.80 ms per 64-column panel, 64
+// workgroups 0.61 ms, 32 workgroups 0.53 ms, 16 (global-memory slabs)
+// 0.86 ms; eight panels per launch already take 31 workgroups each.
+constexpr int kPanelMaxG = 32;
+
 Geometry panel_geometry(int L, int batch) {
     // Slab in LDS when every workgroup of the launch can be resident with it.
     const int limit = lds_limit();
     if (limit > 0) {
         const int max_rows = (limit - kStaticLds) / (kNB * (int)sizeof(double));
-        for (int R = 64; R <= max_rows; R += 16) {
+        // Taller slabs than the LDS holds fall back to the most rows it does.
+        const int rmin = std::max(64, std::min(((L + kPanelMaxG - 1) / kPanelMaxG + 15) / 16 * 16, max_rows / 16 * 16));
+        for (int R = rmin; R <= max_rows; R += 16) {
             const int G = (L + R - 1) / R;
             if (G * batch <= lds_coresident(R)) {
                 const int rows = (L + G - 1) / G;

@@ -127,10 +127,9 @@ def exact_h_error(H, sigma, V):
 
 
 def test_many_panel_workgroups(z):
-    # n = 4096, r = 4: the QR step's panels (4160 live rows) run 65 LDS-slab
-    # workgroups per matrix, 260 in all, more than the global-memory panel
-    # variant could hold at once; the per-workgroup partial sums and flags
-    # are sized for the larger of the two.  H is compared with the exact
+    # n = 4096, r = 4: the QR step's panels (4160 live rows) run 29 LDS-slab
+    # workgroups per matrix (the per-matrix cap), 116 in all, with every
+    # column's exchange across them.  H is compared with the exact
     # V diag(sigma) V^T and the errors are recomputed on the host.
     A, U, sig, V = W.svd_matrix(4096, 4096, 1e12, 1400, 2400)
     Qp, H, info = z.pd(dev(A), alpha=1.0, l=1e-12, r=4, compute_errors=1)
