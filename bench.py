@@ -338,6 +338,33 @@ def bench_batched(args):
         _, _, infos = z.pd_batched(mats, alphas=[1.0] * len(mats), ls=ls, batch_streams=args.batch_streams)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
+    # One more call with per-kernel statistics (HIP events on each worker's
+    # stream) for the roofline of the kernel with the largest GPU time; the
+    # solves overlap, so these are busy times of concurrent launches.
+    zolo.stats_reset()
+    zolo.stats_enable(True)
+    z.pd_batched(mats, alphas=[1.0] * len(mats), ls=ls, batch_streams=args.batch_streams)
+    torch.cuda.synchronize()
+    zolo.stats_enable(False)
+    st = zolo.stats()
+    kname, (kl, kms, kfl, kby) = max(st.items(), key=lambda kv: kv[1][1])
+    if kname.startswith("panel"):
+        # The panel's algorithmic bytes: its slab read once and written once.
+        ach = (kby / kl) / (kms / kl * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": kname, "achieved": ach, "peak": 8000.0, "unit": "GB/s",
+                "frac": ach / 8000.0, "traffic": None, "mean_launch_ms": kms / kl, "launches_per_call": kl,
+                "note": "single-workgroup panels of concurrent solves: latency-bound per column"}
+    elif kfl > 0:
+        ach = (kfl / kl) / (kms / kl * 1e-3) / 1e12
+        roof = {"bound": "mfma", "kernel": kname, "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / FP64_PEAK_TFLOPS, "traffic": None, "mean_launch_ms": kms / kl,
+                "launches_per_call": kl}
+    else:
+        roof = {"bound": "latency", "kernel": kname, "achieved": None, "peak": None, "unit": None, "frac": None,
+                "traffic": None, "mean_launch_ms": kms / kl, "launches_per_call": kl,
+                "note": "largest share is a kernel without a flop model (panel or factorisation latency)"}
+    kernels = {k: {"launches": v[0], "busy_ms": v[1], "tflops": (v[2] / (v[1] * 1e-3) / 1e12) if v[1] > 0 else None}
+               for k, v in sorted(st.items(), key=lambda kv: -kv[1][1])[:10]}
     fl = sum(inf["flops_paper"] for inf in infos)
     # accuracy on a sample of the batch
     errs = []
@@ -354,7 +381,8 @@ def bench_batched(args):
            "matrices_per_s": len(specs) / dt,
            "r_histogram": {str(k): sum(1 for i in infos if i["r"] == k) for k in range(1, 9)},
            "max_bwd_err_sampled": max(e[0] for e in errs), "max_orth_err_sampled": max(e[1] for e in errs),
-           "not_converged": sum(1 for i in infos if i["status"] != 0)}
+           "not_converged": sum(1 for i in infos if i["status"] != 0), "roofline": roof,
+           "kernels_busy_ms": kernels}
     print(json.dumps(out), flush=True)
     z.close()
 

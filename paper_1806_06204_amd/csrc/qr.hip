@@ -597,7 +597,8 @@ hipError_t run_panel(int m, int e, int p, int nb, double* M, long long ld, long 
     if (geo.G == 1) {
         // One workgroup per matrix needs no co-residency: an ordinary launch
         // on the solve's own stream, free to overlap other solves.
-        StatScope sc(geo.lds ? "panel_kernel<lds>" : "panel_kernel<global>", st, 4.0 * L * (double)nb * nb * batch);
+        StatScope sc(geo.lds ? "panel_kernel<lds>" : "panel_kernel<global>", st, 4.0 * L * (double)nb * nb * batch,
+                     16.0 * L * (double)nb * batch);
         if (geo.lds)
             panel_kernel<true><<<batch, kPT, (size_t)geo.rows * kNB * sizeof(double), st>>>(pa);
         else
@@ -614,7 +615,8 @@ hipError_t run_panel(int m, int e, int p, int nb, double* M, long long ld, long 
         if ((err = hipEventRecord(w.ev_ready, st)) != hipSuccess) return err;
         if ((err = hipStreamWaitEvent(ps, w.ev_ready, 0)) != hipSuccess) return err;
     }
-    StatScope sc(geo.lds ? "panel_kernel<lds>" : "panel_kernel<global>", ps, 4.0 * L * (double)nb * nb * batch);
+    StatScope sc(geo.lds ? "panel_kernel<lds>" : "panel_kernel<global>", ps, 4.0 * L * (double)nb * nb * batch,
+                 16.0 * L * (double)nb * batch);
     if (geo.lds)
         err = hipLaunchCooperativeKernel((const void*)panel_kernel<true>, dim3(pa.G * batch), dim3(kPT), args,
                                          (size_t)geo.rows * kNB * sizeof(double), ps);

@@ -372,3 +372,29 @@ def test_time_policy_picks_least_predicted(z):
     assert info["status"] == 0 and info["bwd_err"] <= BAR and info["orth_err"] <= BAR
     Ho = oz.zolo_pd(A, 1.0, 1e-14, best)[1]
     assert np.linalg.norm(H.cpu().numpy() - Ho) <= 1e-12 * np.linalg.norm(Ho)
+
+
+def test_batched_512_uneven_all_exact(z):
+    # The 512-matrix uneven workload (n ~ U{64..1024}, m ~ U{n..2n}, log10
+    # kappa ~ U[2, 12], r by the two-iteration rule) in one zolo_pd_batched
+    # call on 16 worker streams: every matrix converged, backward error and
+    # orthogonality <= 1e-13 recomputed on the host, and H against the exact
+    # V diag(sigma) V^T (<= 1e-12).
+    import torch
+    from paper_1806_06204_amd import zolo
+    specs = W.batch_specs(count=512, seed=4000)
+    built = [W.svd_matrix(sp["m"], sp["n"], sp["kappa"], sp["seed_u"], sp["seed_v"]) for sp in specs]
+    print("  512 matrices generated", flush=True)
+    As = [zolo.to_device(b[0]) for b in built]
+    Qs, Hs, infos = z.pd_batched(As, alphas=[1.0] * len(As), ls=[1.0 / sp["kappa"] for sp in specs])
+    worst = [0.0, 0.0, 0.0]
+    for (A, U, sig, V), Q, H, inf in zip(built, Qs, Hs, infos):
+        assert inf["status"] == 0, inf
+        Qn, Hn = Q.cpu().numpy(), H.cpu().numpy()
+        bwd, orth = host_errors(A, Qn, Hn)
+        Vt = torch.from_numpy(V)
+        Hx = ((Vt * torch.from_numpy(sig)) @ Vt.T).numpy()
+        dh = np.linalg.norm(Hn - Hx) / np.linalg.norm(Hx)
+        worst = [max(worst[0], bwd), max(worst[1], orth), max(worst[2], dh)]
+    print(f"  worst over 512: bwd={worst[0]:.2e} orth={worst[1]:.2e} dH_exact={worst[2]:.2e}", flush=True)
+    assert worst[0] <= BAR and worst[1] <= BAR and worst[2] <= 1e-12
