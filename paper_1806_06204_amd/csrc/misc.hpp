@@ -79,7 +79,7 @@ struct QrWork {
     bool single_panels = false;   // one workgroup per matrix for panels of few rows (see run_panel)
     double* Rd = nullptr;         // batch * npanels * kPanelNB^2 doubles (R diagonal blocks)
     double* S = nullptr;          // qr_s_elems(batch) doubles
-    double* partials = nullptr;   // batch * 2 * maxG * 2 * kPanelNB doubles
+    double* partials = nullptr;   // qr_partials_elems: per-workgroup exchange slots (kPanelSlot doubles, two parities)
     unsigned* flags = nullptr;    // qr_flag_elems: per-workgroup panel sequence flags
     size_t flag_elems = 0;
     int* error_flag = nullptr;    // 1 int
@@ -101,16 +101,22 @@ inline size_t qr_tb_elems(int n, int batch) {
 }
 
 // Doubles each QrWork array needs for m x n, `batch` matrices, e extra rows.
-inline size_t qr_partials_elems(int m, int e, int batch, int max_coresident) {
+// Panel exchange slot of one workgroup: the largest exchange is the one at
+// the end of a 16-column leaf, 16 x (kPanelNB - 16) sums.
+constexpr int kPanelSlot = 16 * (kPanelNB - 16);
+inline int qr_panel_groups(int m, int e, int batch, int max_coresident) {
     int G = (m + e + 63) / 64;  // the most workgroups any row target can ask for
     int cap = max_coresident / (batch > 0 ? batch : 1);
     if (cap < 1) cap = 1;
     if (G > cap) G = cap;
     if (G < 1) G = 1;
-    return (size_t)batch * 2 * (G + 1) * 2 * kPanelNB;
+    return G;
+}
+inline size_t qr_partials_elems(int m, int e, int batch, int max_coresident) {
+    return (size_t)batch * 2 * (qr_panel_groups(m, e, batch, max_coresident) + 1) * kPanelSlot;
 }
 inline size_t qr_flag_elems(int m, int e, int batch, int max_coresident) {
-    return qr_partials_elems(m, e, batch, max_coresident) / (4 * kPanelNB);
+    return (size_t)batch * (qr_panel_groups(m, e, batch, max_coresident) + 1);
 }
 
 // M_b[0:m] = X (ld ldx; X null: leave the dense block), M_b[m:m+n] = pivots[b] * I, b < batch <= 16.

@@ -14,15 +14,19 @@
 //
 // Panel: one launch per panel factors all b together (a cooperative launch
 // when a matrix takes more than one workgroup).  Each matrix gets G
-// workgroups, each owning a slab of the panel's live rows.  For
-// column k a workgroup applies reflector k-1 to its rows and, in the same pass,
-// accumulates the dot products of column k (below the pivot) with every panel
-// column and picks up the pivot row; one cross-workgroup reduction of these
-// 2 NB numbers gives the norm, the update coefficients of the remaining
-// columns and the next column of T (compact WY, Q = I - V T V^T).  The
-// reduction sums partials in a fixed order; its barrier waits a bounded time.
-// On exit the panel's top block holds V explicitly (unit diagonal, zeros above)
-// and the R diagonal block is saved apart.
+// workgroups, each owning a slab of the panel's live rows.  The panel's 64
+// columns are factored in leaves of 16.  For column k a workgroup applies
+// reflector k-1 to the leaf's columns on its rows and, in the same pass,
+// accumulates the dot products of column k (below the pivot) with the
+// leaf's columns and picks up the pivot row; one cross-workgroup reduction
+// of these 32 numbers gives the norm, the update coefficients of the leaf's
+// remaining columns and the next column of the leaf's T (compact WY,
+// Q = I - V T V^T).  At the end of a leaf one MFMA reduction and one
+// exchange give V_leaf^T times the other panel columns, from which the
+// panel's T is extended and the rest of the panel takes the leaf's block
+// reflector.  Every reduction sums partials in a fixed order; its barrier
+// waits a bounded time.  On exit the panel's top block holds V explicitly
+// (unit diagonal, zeros above) and the R diagonal block is saved apart.
 //
 // Trailing update and Q formation are GEMMs on the MFMA kernel over the live
 // rows:  W = V^T C,  W2 = T^T W,  C -= V W2  (ORGQR: T instead of T^T, last
@@ -46,14 +50,25 @@ namespace zolo {
 namespace {
 
 constexpr int kNB = kPanelNB;
-constexpr int kRG = 2;                   // row groups: waves that split a column group's rows
-constexpr int kPT = 256 * kRG;           // threads per panel workgroup
-constexpr int kColsPerWave = kNB / 4;    // panel columns owned by each wave
+constexpr int kLW = 16;                  // leaf width: columns factored one exchange at a time
+constexpr int kNL = kNB / kLW;           // leaves per panel
+constexpr int kOther = kNB - kLW;        // panel columns outside one leaf
+constexpr int kPT = 512;                 // threads per panel workgroup
+constexpr int kRG = kPT / 64;            // row groups: every wave owns the leaf's columns over its rows
+// Exchanges of one panel: one per column and one at the end of each leaf.
+constexpr int kPanelExchanges = kNB + kNL;
+static_assert(kLW * kOther == kPanelSlot, "exchange slot sized for the leaf-end sums");
 // Slab rows per lane loaded together in the column sweep: two when the
-// slab stays in global memory (latency of L2; with two row groups, four
-// rows of each column group are in flight), one from LDS.
+// slab stays in global memory (latency of L2), one from LDS.
 template <bool InLds>
 constexpr int kRowUnroll = InLds ? 1 : 2;
+// Rows per lane step of the leaf-end MFMA reduction (loads issued together).
+template <bool InLds>
+constexpr int kQuadUnroll = InLds ? 2 : 4;
+// Cache-policy operand of a buffer load that makes it coherent at agent
+// scope (sc1 on gfx950), and the fourth word of a raw buffer resource.
+constexpr int kCoherentLoad = 16;
+constexpr int kBufferRsrcWord3 = 0x00020000;
 // s_waitcnt immediate (gfx9 encoding) that waits for vmcnt == 0 only:
 // vmcnt bits [3:0],[15:14] = 0, expcnt [6:4] = 7, lgkmcnt [11:8] = 15.
 constexpr int kWaitVmcnt0 = 0x0F70;
@@ -63,9 +78,9 @@ struct PanelArgs {
     double* P; long long ld, sp;         // panel top-left (row p0, column p0) of matrix 0
     double* T; long long st;             // T_b, kNB x kNB column-major
     double* Rd; long long srd;           // R diagonal block out, kNB x kNB
-    double* partials;                    // [batch][2][G][2 kNB]
-    unsigned* flags;                     // [batch][G]: last column each workgroup published
-    unsigned seq;                        // flags of this panel's column k read seq + k + 1
+    double* partials;                    // [batch][2][G][kPanelSlot]
+    unsigned* flags;                     // [batch][G]: last exchange each workgroup published
+    unsigned seq;                        // exchange x of this panel is published as seq + x + 1
     int* error_flag;
     unsigned spin_limit;
     int lds_stride;                      // InLds: leading dimension of the slab in LDS
@@ -88,15 +103,34 @@ __device__ inline void butterfly_step(double (&h)[16], int lane) {
     }
 }
 
+// Blocked panel.  The panel's columns are factored in leaves of kLW = 16.
+// Inside a leaf, column k takes one sweep over the slab's rows that applies
+// reflector k-1 to the leaf's later columns and accumulates the dot products
+// of column k below its pivot with the leaf's 16 columns, then one exchange
+// of those 16 sums and of the pivot row's 16 entries, which give the norm,
+// the update coefficients of the leaf's later columns and the next column of
+// the leaf's own compact-WY factor T_s.  At the end of a leaf, one MFMA
+// reduction over the rows forms W = V_s^T [V_prev, C] (V_s: the leaf's
+// reflectors; V_prev: the earlier leaves'; C: the later columns of the
+// panel), one exchange sums it over the workgroups, the first workgroup
+// merges T = [T1, -T1 (V_prev^T V_s) T_s; 0, T_s], and every workgroup
+// applies the leaf's block reflector to C:  C -= V_s (T_s^T (V_s^T C)).
+// Against one sweep of all 64 columns per column, this sweeps 16 columns per
+// column and the whole panel twice per leaf.
 template <bool InLds>
 __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
     extern __shared__ double smem[];
-    __shared__ double s_d[kNB], s_pr[kNB], s_coef[kNB], s_z[kNB], s_w[2 * kNB];
-    __shared__ double s_wp[kRG][kNB];  // column sums of each row group
-    __shared__ double s_tau;             // tau of the column whose T column is still to be formed
     __shared__ double s_T[kNB * (kNB + 1) / 2];  // upper T packed by columns: T[i][l] at l (l + 1) / 2 + i
+    // Leaf-end sums W[i][q] at i * kOther + q (i: leaf column, q: other
+    // column, the earlier leaves' columns first).  While a leaf's columns
+    // are factored, its first kRG * kLW entries hold each wave's column sums.
+    __shared__ double s_W[kLW * kOther];
+    __shared__ double s_coef[kLW], s_z[kLW];
+    __shared__ double s_rfl[4];          // beta, tau, scale of the latest reflector
+    double* const s_wp = s_W;
     const int g = blockIdx.x % a.G, b = blockIdx.x / a.G;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
     const long long ld = a.ld;
     double* __restrict__ P = a.P + b * a.sp;
     const int r0 = g * a.rows_per_wg;
@@ -110,246 +144,393 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
             X[rl + j * xld] = P[(r0 + rl) + j * ld];
         }
     }
-    if (tid < kNB) {
-        s_coef[tid] = 0.0;
-        s_w[kNB + tid] = 0.0;
-    }
     __syncthreads();
     unsigned* flg = a.flags + (long long)b * a.G;
-    // Column kk of T: T[0:kk, kk] = -tau T[0:kk, 0:kk] z, T[kk][kk] = tau,
-    // with z = V[:, 0:kk]^T v_kk (s_z) and tau (s_tau) of column kk; by
-    // threads 64 .. 64 + kk of the first workgroup of each matrix (the only
-    // one that keeps T).  It runs during the next column's exchange, while
-    // wave 0 waits for the other workgroups, so that this workgroup, which
-    // every other one waits for, does not publish its partial sums late.
-    auto t_update = [&](int kk) __attribute__((always_inline)) {
-        const int j = tid - 64;
-        if (g != 0 || j < 0 || j > kk) return;
-        const double tk = s_tau;
-        if (j < kk) {
-            // Four partial sums break the dependent chain of LDS reads.
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-            int l = j;
-            for (; l + 3 < kk; l += 4) {
-                s0 += s_T[l * (l + 1) / 2 + j] * s_z[l];
-                s1 += s_T[(l + 1) * (l + 2) / 2 + j] * s_z[l + 1];
-                s2 += s_T[(l + 2) * (l + 3) / 2 + j] * s_z[l + 2];
-                s3 += s_T[(l + 3) * (l + 4) / 2 + j] * s_z[l + 3];
-            }
-            for (; l < kk; ++l) s0 += s_T[l * (l + 1) / 2 + j] * s_z[l];
-            s_T[kk * (kk + 1) / 2 + j] = -tk * ((s0 + s1) + (s2 + s3));
-        } else {
-            s_T[kk * (kk + 1) / 2 + kk] = tk;
+    unsigned ex = 0;  // exchanges done in this panel
+
+    // Sums cnt values of src over the matrix's workgroups into dst (LDS;
+    // src may be dst).  Thread t publishes src[t], which it wrote itself or
+    // which a barrier made visible.  Partials, flags and polls are
+    // device-coherent (agent-scope) relaxed atomics.  A workgroup barrier
+    // does not wait for outstanding global stores, so every storing wave
+    // waits for its partial stores to be acknowledged (vmcnt 0) before the
+    // barrier after which thread 0 raises the workgroup's flag; without that
+    // wait another workgroup can see the flag and read a stale partial.  No
+    // release/acquire fences: those would write back or invalidate the whole
+    // L2 on every exchange.  Each workgroup has a flag of its own, set to the
+    // exchange's sequence number, and thread t polls the flag of workgroup t.
+    // Slots alternate between two parities: a workgroup can only rewrite a
+    // slot after every other workgroup has published the exchange after the
+    // one that read it.  The sums are taken in workgroup order.
+    auto exchange = [&](const double* src, double* dst, int cnt) __attribute__((always_inline)) {
+        if (a.G == 1) {
+            if (src != dst)
+                for (int t = tid; t < cnt; t += kPT) dst[t] = src[t];
+            __syncthreads();
+            ++ex;
+            return;
         }
+        double* part = a.partials + (((long long)b * 2 + (ex & 1)) * a.G + g) * kPanelSlot;
+        for (int t = tid; t < cnt; t += kPT)
+            __hip_atomic_store(&part[t], src[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+        __syncthreads();
+        const unsigned target = a.seq + ex + 1u;
+        if (tid == 0) __hip_atomic_store(&flg[g], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int t = tid; t < a.G; t += kPT) {
+            if (t == g) continue;
+            unsigned spins = 0;
+            while (__hip_atomic_load(&flg[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                if (++spins > a.spin_limit) {
+                    atomicOr(a.error_flag, 1);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __syncthreads();
+        // The partials are read with plain buffer loads that carry the
+        // agent-coherence cache policy (sc1, what an agent-scope relaxed
+        // atomic load uses): the compiler keeps atomic loads in order and
+        // interleaved their uses with them, one memory round trip per load;
+        // plain loads of 32 partials are all issued before the first wait.
+        // The barrier after the polls orders them after the flags were seen.
+        const double* pb = a.partials + ((long long)b * 2 + (ex & 1)) * a.G * kPanelSlot;
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc((void*)pb, (short)0, 0x7fffffff, kBufferRsrcWord3);
+        for (int t = tid; t < cnt; t += kPT) {
+            // Thirty-two loads in flight per round (clamped index, padded
+            // with +0.0, which leaves the in-order sum unchanged).
+            double sum = 0.0;
+            for (int gg = 0; gg < a.G; gg += 32) {
+                double v[32];
+#pragma unroll
+                for (int u = 0; u < 32; ++u) {
+                    const int gi = min(gg + u, a.G - 1);
+                    v[u] = __builtin_bit_cast(
+                        double, __builtin_amdgcn_raw_buffer_load_b64(rs, (gi * kPanelSlot + t) * 8, 0, kCoherentLoad));
+                }
+#pragma unroll
+                for (int u = 0; u < 32; ++u) sum += gg + u < a.G ? v[u] : 0.0;
+            }
+            dst[t] = sum;
+        }
+        __syncthreads();
+        ++ex;
     };
 
-    for (int k = 0; k < nb; ++k) {
-        // Phase A: reflector k-1 on the columns > k (rows >= k-1) and the dot
-        // products of column k below the pivot with every panel column.  Wave
-        // w owns columns 16 (w % 4) .. 16 (w % 4) + 15 over the rows of row
-        // group w / 4 (every kRG-th block of 64 rows); its index is made
-        // scalar so that every per-column condition is uniform.
-        const int wv = __builtin_amdgcn_readfirstlane(wave);
-        const int cw = (wv & 3) * kColsPerWave, rg = wv >> 2;
-        double acc[kColsPerWave], cq[kColsPerWave];
-#pragma unroll
-        for (int q = 0; q < kColsPerWave; ++q) {
-            const int i = cw + q;
-            const double c = s_coef[i];
-            acc[q] = 0.0;
-            cq[q] = (k > 0 && i > k && i < nb) ? c : 0.0;
-        }
-        const double ck = k > 0 ? s_coef[k] : 0.0;
-        const int lo = max(r0, k > 0 ? k - 1 : 0);
-        constexpr int U = kRowUnroll<InLds>;
-        // Rows are taken U at a time, all their loads first (the
-        // slab's rows are independent; this keeps several loads in flight),
-        // then the arithmetic and the stores row by row in increasing order,
-        // so each lane accumulates its rows in the same order as one at a time.
-        auto load_row = [&](int row, double (&val)[kColsPerWave], double& vraw, double& xraw)
-                            __attribute__((always_inline)) {
-            const int rl = row - r0;
-#pragma unroll
-            for (int q = 0; q < kColsPerWave; ++q) {
-                const int i = min(cw + q, nb - 1);
-                val[q] = X[rl + i * xld];
+    // The same exchange done by wave 0 alone, for at most 64 values held one
+    // per lane (no workgroup barrier: the wave's own stores are acknowledged
+    // before its lane 0 raises the flag).  Returns lane l's sum over the
+    // matrix's workgroups (lanes >= cnt: 0).
+    auto exchange_wave = [&](double val, int cnt) __attribute__((always_inline)) -> double {
+        double* part = a.partials + (((long long)b * 2 + (ex & 1)) * a.G + g) * kPanelSlot;
+        if (lane < cnt) __hip_atomic_store(&part[lane], val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+        const unsigned target = a.seq + ex + 1u;
+        if (lane == 0) __hip_atomic_store(&flg[g], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int t = lane; t < a.G; t += 64) {
+            if (t == g) continue;
+            unsigned spins = 0;
+            while (__hip_atomic_load(&flg[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                if (++spins > a.spin_limit) {
+                    atomicOr(a.error_flag, 1);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
             }
-            vraw = k > 0 ? X[rl + (k - 1) * xld] : 0.0;
-            xraw = X[rl + k * xld];
-        };
-        auto finish_row = [&](int row, double (&val)[kColsPerWave], double vraw, double xraw)
-                              __attribute__((always_inline)) {
-            const int rl = row - r0;
-            const double vprev = k > 0 ? (row == k - 1 ? 1.0 : vraw) : 0.0;
-            const double xk = xraw - ck * vprev;
-            const double xa = row > k ? xk : 0.0;  // column k below the pivot
+        }
+        asm volatile("" ::: "memory");  // the partials are read after the polls
+        const double* pb = a.partials + ((long long)b * 2 + (ex & 1)) * a.G * kPanelSlot;
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc((void*)pb, (short)0, 0x7fffffff, kBufferRsrcWord3);
+        double sum = 0.0;
+        if (lane < cnt) {
+            for (int gg = 0; gg < a.G; gg += 32) {
+                double v[32];
 #pragma unroll
-            for (int q = 0; q < kColsPerWave; ++q) {
-                const int i = cw + q;
-                double v = val[q] - cq[q] * vprev;  // cq = 0 leaves columns <= k as they are
-                if (i == k) v = xk;
-                val[q] = v;
-                acc[q] += xa * v;
+                for (int u = 0; u < 32; ++u) {
+                    const int gi = min(gg + u, a.G - 1);
+                    v[u] = __builtin_bit_cast(
+                        double, __builtin_amdgcn_raw_buffer_load_b64(rs, (gi * kPanelSlot + lane) * 8, 0, kCoherentLoad));
+                }
+#pragma unroll
+                for (int u = 0; u < 32; ++u) sum += gg + u < a.G ? v[u] : 0.0;
+            }
+        }
+        return sum;
+    };
+
+    for (int c0 = 0; c0 < nb; c0 += kLW) {
+        const int lw = min(kLW, nb - c0);
+        for (int kk = 0; kk < lw; ++kk) {
+            const int k = c0 + kk;
+            // Sweep: reflector k-1 (inside this leaf) on the leaf's columns
+            // > k-1 (rows >= k-1) and the dot products of column k below the
+            // pivot with the leaf's columns.  Each thread owns the same rows
+            // in every column (r0 + 64 w + lane + 64 kRG j for wave w), so
+            // that it can write column k on its rows after the exchange
+            // without a barrier; per-column conditions are uniform.
+            double acc[kLW], cq[kLW];
+#pragma unroll
+            for (int q = 0; q < kLW; ++q) {
+                const double c = s_coef[q];
+                acc[q] = 0.0;
+                cq[q] = (kk > 0 && q > kk && q < lw) ? c : 0.0;
+            }
+            const double ck = kk > 0 ? s_coef[kk] : 0.0;
+            const int lo = max(r0, kk > 0 ? k - 1 : k);
+            constexpr int U = kRowUnroll<InLds>;
+            // Rows are taken U at a time, all their loads first, then the
+            // arithmetic and the stores row by row in increasing order, so
+            // each lane accumulates its rows in the same order as one at a time.
+            auto load_row = [&](int row, double (&val)[kLW], double& vraw, double& xraw)
+                                __attribute__((always_inline)) {
+                const int rl = row >= lo && row < r1 ? row - r0 : lo - r0;
+#pragma unroll
+                for (int q = 0; q < kLW; ++q) val[q] = X[rl + (c0 + min(q, lw - 1)) * xld];
+                vraw = kk > 0 ? X[rl + (k - 1) * xld] : 0.0;
+                xraw = X[rl + k * xld];
+            };
+            auto finish_row = [&](int row, double (&val)[kLW], double vraw, double xraw)
+                                  __attribute__((always_inline)) {
+                if (row < lo || row >= r1) return;
+                const int rl = row - r0;
+                const double vprev = kk > 0 ? (row == k - 1 ? 1.0 : vraw) : 0.0;
+                const double xk = xraw - ck * vprev;
+                const double xa = row > k ? xk : 0.0;  // column k below the pivot
+#pragma unroll
+                for (int q = 0; q < kLW; ++q) {
+                    double v = val[q] - cq[q] * vprev;  // cq = 0 leaves columns <= k as they are
+                    if (q == kk) v = xk;
+                    val[q] = v;
+                    acc[q] += xa * v;
+                }
+                if (kk > 0) {
+#pragma unroll
+                    for (int q = 0; q < kLW; ++q)
+                        if (q > kk && q < lw) X[rl + (c0 + q) * xld] = val[q];
+                }
+            };
+            constexpr int S = 64 * kRG;  // row stride of a lane
+            const int first = r0 + 64 * wv + lane;
+            for (int row = first; row < r1; row += S * U) {
+                double val[U][kLW], vraw[U], xraw[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) load_row(row + S * u, val[u], vraw[u], xraw[u]);
+#pragma unroll
+                for (int u = 0; u < U; ++u) finish_row(row + S * u, val[u], vraw[u], xraw[u]);
+            }
+            {
+                // The 16 column sums of the wave in one transposing butterfly:
+                // at offsets 32, 16, 8, 4 each lane keeps half of its values and
+                // adds the partner's copy of that half (17 shuffles instead of
+                // 16 x 6); then lane l holds value (l >> 2) & 15 summed over the
+                // 16 lanes that differ in bits 2-5, and offsets 2, 1 finish it.
+                static_assert(kLW == 16, "butterfly written for 16 columns per wave");
+                double h[kLW];
+#pragma unroll
+                for (int q = 0; q < kLW; ++q) h[q] = acc[q];
+                butterfly_step<8, 32>(h, lane);
+                butterfly_step<4, 16>(h, lane);
+                butterfly_step<2, 8>(h, lane);
+                butterfly_step<1, 4>(h, lane);
+                double t = h[0];
+                t += __shfl_xor(t, 2, 64);
+                t += __shfl_xor(t, 1, 64);
+                if ((lane & 3) == 0) s_wp[wv * kLW + ((lane >> 2) & 15)] = t;
+            }
+            __syncthreads();
+            if (wv == 0) {
+                // Wave 0 alone does the column's exchange: lanes 0..15 add
+                // the waves' sums in a fixed order, lanes 16..31 read back the
+                // pivot row after the update if this slab holds it (zero
+                // elsewhere: columns > k were stored above, columns < k are
+                // unchanged and column k is recomputed).
+                double val = 0.0;
+                if (lane < kLW) {
+                    val = s_wp[lane];
+#pragma unroll
+                    for (int q = 1; q < kRG; ++q) val += s_wp[q * kLW + lane];
+                } else if (lane < 2 * kLW && k >= r0 && k < r1) {
+                    const int q = lane - kLW, rl = k - r0;
+                    double v = X[rl + (c0 + min(q, lw - 1)) * xld];
+                    if (q == kk) v -= ck * (kk > 0 ? X[rl + (k - 1) * xld] : 0.0);
+                    val = q < lw ? v : 0.0;
+                }
+                double sum = val;
+                if (a.G > 1) sum = exchange_wave(val, 2 * kLW);
+                // Reflector k on x = [alpha; below], beta = -sign(alpha) |x|,
+                // v = [1; below / (alpha - beta)]  (no cancellation in alpha - beta).
+                const double s2 = __shfl(sum, kk, 64), alpha = __shfl(sum, kLW + kk, 64);
+                double beta, tau, scale;
+                if (s2 == 0.0) {
+                    beta = alpha;
+                    tau = 0.0;
+                    scale = 0.0;
+                } else {
+                    const double nrm = sqrt(alpha * alpha + s2);
+                    beta = alpha >= 0.0 ? -nrm : nrm;
+                    tau = (beta - alpha) / beta;
+                    scale = 1.0 / (alpha - beta);
+                }
+                // v_k^T col (lane > kk) or v_lane^T v_k (lane < kk)
+                const double w = __shfl(sum, kLW + (lane & (kLW - 1)), 64) + scale * sum;
+                if (lane < lw && lane > kk) s_coef[lane] = tau * w;
+                if (lane < kk) s_z[lane] = w;
+                if (lane == 0) {
+                    s_rfl[0] = beta;
+                    s_rfl[1] = tau;
+                    s_rfl[2] = scale;
+                }
+            }
+            ++ex;
+            __syncthreads();
+            const double beta = s_rfl[0], tau = s_rfl[1], scale = s_rfl[2];
+            // Column k on this thread's rows: R entry on row k-1, beta on the
+            // pivot, v below (column k was not stored by the sweep; column
+            // k-1 on these rows was written by this thread).
+            for (int row = first; row < r1; row += S) {
+                if (row < lo) continue;
+                const int rl = row - r0;
+                const double vprev = kk > 0 ? (row == k - 1 ? 1.0 : X[rl + (k - 1) * xld]) : 0.0;
+                const double x = X[rl + k * xld] - ck * vprev;
+                X[rl + k * xld] = row == k ? beta : (row > k ? scale * x : x);
+            }
+            // Column kk of the leaf's T_s (every workgroup keeps T_s):
+            // T[c0+j][k] = -tau sum_l T[c0+j][c0+l] z_l, T[k][k] = tau.
+            // Thread 64 + j forms row j of T_s in every column, so it only
+            // reads entries it wrote itself.
+            if (tid >= 64 && tid <= 64 + kk) {
+                const int j = tid - 64;
+                const int base = k * (k + 1) / 2 + c0;
+                if (j < kk) {
+                    double s0 = 0.0, s1 = 0.0;
+                    int l = j;
+                    for (; l + 1 < kk; l += 2) {
+                        s0 += s_T[(c0 + l) * (c0 + l + 1) / 2 + c0 + j] * s_z[l];
+                        s1 += s_T[(c0 + l + 1) * (c0 + l + 2) / 2 + c0 + j] * s_z[l + 1];
+                    }
+                    for (; l < kk; ++l) s0 += s_T[(c0 + l) * (c0 + l + 1) / 2 + c0 + j] * s_z[l];
+                    s_T[base + j] = -tau * (s0 + s1);
+                } else {
+                    s_T[base + kk] = tau;
+                }
+            }
+        }
+        __syncthreads();  // the leaf's columns and T_s are complete
+
+        // Leaf end: W = V_s^T [V_prev, C] over rows >= c0 (V_s is zero above
+        // row c0, 1 on its diagonal).  Wave w forms the 16 x 16 block of
+        // other columns 16 w .. 16 w + 15 with 16 x 16 x 4 MFMAs: lane l
+        // holds V_s[row][c0 + l % 16] and Y[row][l % 16] for row = base + l / 16.
+        const int nother = nb - lw;
+        if (nother == 0) break;
+        const int nblk = (nother + 15) / 16;
+        const int rs = max(r0, c0);
+        if (wv < nblk) {
+            const int q0 = wv * 16;
+            const int cb = q0 < c0 ? q0 : q0 + lw;  // first column of the block (blocks do not straddle the leaf)
+            const int i = lane & 15;
+            const int ci = c0 + i, cj = cb + i;
+            const bool iok = i < lw, jok = cj < nb && (q0 + i) < nother;
+            d4 w4 = d4{0, 0, 0, 0};
+            constexpr int UQ = kQuadUnroll<InLds>;
+            int base = rs;
+            for (; base < r1; base += 4 * UQ) {
+                double av[UQ], bv[UQ];
+#pragma unroll
+                for (int u = 0; u < UQ; ++u) {
+                    const int r = base + 4 * u + (lane >> 4);
+                    const bool rok = r < r1;
+                    const int rl = rok ? r - r0 : 0;
+                    const double xa = X[rl + (iok ? ci : c0) * xld];
+                    const double xb = X[rl + (jok ? cj : c0) * xld];
+                    av[u] = (rok && iok && r >= ci) ? (r == ci ? 1.0 : xa) : 0.0;
+                    bv[u] = (rok && jok) ? xb : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < UQ; ++u) w4 = mfma_f64_16x16x4(av[u], bv[u], w4);
             }
 #pragma unroll
-            for (int q = 0; q < kColsPerWave; ++q) {
-                const int i = cw + q;
-                if (k > 0 && i > k && i < nb) X[rl + i * xld] = val[q];
+            for (int e = 0; e < 4; ++e) {
+                const int ii = Mfma<double>::row(lane, e);
+                s_W[ii * kOther + q0 + i] = w4[e];
             }
-        };
-        constexpr int S = 64 * kRG;  // row stride of a lane
-        int row = lo + 64 * rg + lane;
-        for (; row + S * (U - 1) < r1; row += S * U) {
-            double val[U][kColsPerWave], vraw[U], xraw[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) load_row(row + S * u, val[u], vraw[u], xraw[u]);
-#pragma unroll
-            for (int u = 0; u < U; ++u) finish_row(row + S * u, val[u], vraw[u], xraw[u]);
-        }
-        for (; row < r1; row += S) {
-            double val[kColsPerWave], vraw, xraw;
-            load_row(row, val, vraw, xraw);
-            finish_row(row, val, vraw, xraw);
-        }
-        {
-            // The 16 column sums of the wave in one transposing butterfly:
-            // at offsets 32, 16, 8, 4 each lane keeps half of its values and
-            // adds the partner's copy of that half (17 shuffles instead of
-            // 16 x 6); then lane l holds value (l >> 2) & 15 summed over the
-            // 16 lanes that differ in bits 2-5, and offsets 2, 1 finish it.
-            static_assert(kColsPerWave == 16, "butterfly written for 16 columns per wave");
-            double h[kColsPerWave];
-#pragma unroll
-            for (int q = 0; q < kColsPerWave; ++q) h[q] = acc[q];
-            butterfly_step<8, 32>(h, lane);
-            butterfly_step<4, 16>(h, lane);
-            butterfly_step<2, 8>(h, lane);
-            butterfly_step<1, 4>(h, lane);
-            double t = h[0];
-            t += __shfl_xor(t, 2, 64);
-            t += __shfl_xor(t, 1, 64);
-            const int i = cw + ((lane >> 2) & 15);
-            if ((lane & 3) == 0 && i < nb) s_wp[rg][i] = t;
         }
         __syncthreads();
-        // The row groups' sums, added in a fixed order.
-        if (tid < nb) {
-            double t = s_wp[0][tid];
-#pragma unroll
-            for (int q = 1; q < kRG; ++q) t += s_wp[q][tid];
-            s_w[tid] = t;
-        }
-        // The pivot row after the update, read back by the workgroup that owns
-        // it (its slots stay zero elsewhere): columns > k were stored above,
-        // columns < k are unchanged and column k is recomputed.
-        if (k >= r0 && k < r1 && tid < nb) {
-            const int rl = k - r0;
-            double v = X[rl + tid * xld];
-            if (tid == k) v -= ck * (k > 0 ? X[rl + (k - 1) * xld] : 0.0);
-            s_w[kNB + tid] = v;
-        }
+        exchange(s_W, s_W, lw * kOther);
 
-        // Phase B: publish, wait for the other slabs of this matrix, sum in order.
-        // Partials, flags and polls are device-coherent (agent-scope) atomics.
-        // A workgroup barrier does not wait for outstanding global stores, so
-        // the storing wave (wave 0, the same wave that then raises the
-        // workgroup's flag) waits for its partial stores to be acknowledged
-        // before the barrier; without that wait another workgroup can see the
-        // flag and read a stale partial.  No release/acquire fences: those
-        // would write back or invalidate the whole L2 on every column.  Each
-        // workgroup has a flag of its own (no atomic read-modify-write on one
-        // shared word), and thread t polls the flag of workgroup t.
-        // One workgroup per matrix: its own sums are the totals.
-        if (a.G == 1) {
-            if (k > 0) t_update(k - 1);
-            if (tid < nb) {
-                s_d[tid] = s_w[tid];
-                s_pr[tid] = s_w[kNB + tid];
-            }
-            __syncthreads();
-        } else {
-            double* part = a.partials + (((long long)b * 2 + (k & 1)) * a.G + g) * (2 * kNB);
-            if (tid < nb) {
-                __hip_atomic_store(&part[tid], s_w[tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(&part[kNB + tid], s_w[kNB + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
-            }
-            __syncthreads();
-            const unsigned target = a.seq + (unsigned)k + 1u;
-            if (tid == 0) __hip_atomic_store(&flg[g], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (k > 0) t_update(k - 1);
-            for (int t = tid; t < a.G; t += kPT) {
-                if (t == g) continue;
-                unsigned spins = 0;
-                while (__hip_atomic_load(&flg[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                    if (++spins > a.spin_limit) {
-                        atomicOr(a.error_flag, 1);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
+        if (g == 0 && c0 > 0) {
+            // T[0:c0, c0:c0+lw] = -T1 (V_prev^T V_s) T_s, first M = (V_prev^T V_s) T_s.
+            double m[2] = {0.0, 0.0};
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int t = tid + h * kPT;
+                if (t < c0 * lw) {
+                    const int j = t / lw, i = t % lw;
+                    double s = 0.0;
+                    for (int l = 0; l <= i; ++l)
+                        s += s_W[l * kOther + j] * s_T[(c0 + i) * (c0 + i + 1) / 2 + c0 + l];
+                    m[h] = s;
                 }
             }
             __syncthreads();
-            if (tid < 2 * nb) {
-                // Coherent loads have memory latency: issue them eight at a time
-                // and add in a fixed order.
-                const int idx = tid < nb ? tid : kNB + (tid - nb);
-                const double* pb = a.partials + ((long long)b * 2 + (k & 1)) * a.G * (2 * kNB);
-                // Thirty-two loads in flight per round (clamped index, padded
-                // with +0.0, which leaves the in-order sum unchanged).
-                double sum = 0.0;
-                for (int gg = 0; gg < a.G; gg += 32) {
-                    double v[32];
 #pragma unroll
-                    for (int u = 0; u < 32; ++u) {
-                        const int gi = min(gg + u, a.G - 1);
-                        const double x = __hip_atomic_load(&pb[gi * (2 * kNB) + idx], __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_AGENT);
-                        v[u] = gg + u < a.G ? x : 0.0;
-                    }
-#pragma unroll
-                    for (int u = 0; u < 32; ++u) sum += v[u];
-                }
-                if (tid < nb) s_d[tid] = sum;
-                else s_pr[tid - nb] = sum;
+            for (int h = 0; h < 2; ++h) {
+                const int t = tid + h * kPT;
+                if (t < c0 * lw) s_W[(t % lw) * kOther + t / lw] = m[h];
             }
             __syncthreads();
-
+            for (int t = tid; t < c0 * lw; t += kPT) {
+                const int jj = t / lw, i = t % lw;
+                double s = 0.0;
+                for (int j = jj; j < c0; ++j) s += s_T[j * (j + 1) / 2 + jj] * s_W[i * kOther + j];
+                s_T[(c0 + i) * (c0 + i + 1) / 2 + jj] = -s;
+            }
         }
-
-        // Phase C: reflector k on x = [alpha; below], beta = -sign(alpha) |x|,
-        // v = [1; below / (alpha - beta)]  (no cancellation in alpha - beta).
-        const double alpha = s_pr[k], s2 = s_d[k];
-        double beta, tau, scale;
-        if (s2 == 0.0) {
-            beta = alpha;
-            tau = 0.0;
-            scale = 0.0;
-        } else {
-            const double nrm = sqrt(alpha * alpha + s2);
-            beta = alpha >= 0.0 ? -nrm : nrm;
-            tau = (beta - alpha) / beta;
-            scale = 1.0 / (alpha - beta);
+        const int nc = nb - c0 - lw;  // later columns of the panel
+        if (nc > 0) {
+            // W2 = T_s^T (V_s^T C) in place of V_s^T C, then C -= V_s W2.
+            double m[2] = {0.0, 0.0};
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int t = tid + h * kPT;
+                if (t < lw * nc) {
+                    const int i = t / nc, q = c0 + t % nc;
+                    double s = 0.0;
+                    for (int l = 0; l <= i; ++l)
+                        s += s_T[(c0 + i) * (c0 + i + 1) / 2 + c0 + l] * s_W[l * kOther + q];
+                    m[h] = s;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int t = tid + h * kPT;
+                if (t < lw * nc) s_W[(t / nc) * kOther + c0 + t % nc] = m[h];
+            }
+            __syncthreads();
+            for (int r = rs + tid; r < r1; r += kPT) {
+                const int rl = r - r0;
+                double v[kLW];
+#pragma unroll
+                for (int i = 0; i < kLW; ++i) {
+                    const int ci = c0 + i;
+                    const double x = X[rl + min(ci, nb - 1) * xld];
+                    v[i] = (i < lw && r >= ci) ? (r == ci ? 1.0 : x) : 0.0;
+                }
+                for (int q = 0; q < nc; ++q) {
+                    const int col = c0 + lw + q;
+                    double s = 0.0;
+#pragma unroll
+                    for (int i = 0; i < kLW; ++i) s += v[i] * s_W[i * kOther + c0 + q];
+                    X[rl + col * xld] -= s;
+                }
+            }
         }
-        if (tid < nb) {
-            const double w = s_pr[tid] + scale * s_d[tid];  // v_k^T col (tid > k) or v_tid^T v_k (tid < k)
-            if (tid > k) s_coef[tid] = tau * w;
-            if (tid < k) s_z[tid] = w;
-        }
-        if (g == 0 && tid == 0) s_tau = tau;  // its T column is formed during the next exchange
-        __syncthreads();
-        // Phase D: column k: R entry on row k-1, beta on the pivot, v below.
-        for (int row = max(r0, k > 0 ? k - 1 : 0) + tid; row < r1; row += kPT) {
-            const int rl = row - r0;
-            const double vprev = k > 0 ? (row == k - 1 ? 1.0 : X[rl + (k - 1) * xld]) : 0.0;
-            const double x = X[rl + k * xld] - ck * vprev;
-            X[rl + k * xld] = row == k ? beta : (row > k ? scale * x : x);
-        }
-        if (tid < kNB) s_w[kNB + tid] = 0.0;  // pivot-row slots of the next column
         __syncthreads();
     }
-    t_update(nb - 1);  // the last column's T column (s_z, s_tau published by the loop's last barrier)
-    __syncthreads();
     // Save the R diagonal block; make V's top block explicit (1 on the
     // diagonal, 0 above) so the GEMMs can use the stored panel as V.
     double* Rd = a.Rd + b * a.srd;
@@ -439,7 +620,7 @@ constexpr int kPanelRowsTarget = 256;
 // 3.34 s with cooperative panels, 2.81 s with single-workgroup panels.
 constexpr int kSinglePanelRows = 2304;
 
-constexpr int kStaticLds = (6 * kNB + kRG * kNB + kNB * (kNB + 1) / 2) * 8 + 256;
+constexpr int kStaticLds = (kNB * (kNB + 1) / 2 + kLW * kOther + 4 * kLW) * 8 + 256;
 
 int lds_limit() {
     static int v = [] {
@@ -588,7 +769,7 @@ hipError_t run_panel(int m, int e, int p, int nb, double* M, long long ld, long 
     pa.Rd = w.Rd + (long long)p * kNB * kNB; pa.srd = stT;
     pa.partials = w.partials;
     pa.flags = w.flags;
-    pa.seq = (unsigned)p * kNB;
+    pa.seq = (unsigned)p * kPanelExchanges;
     pa.error_flag = w.error_flag;
     pa.spin_limit = 1u << 24;
     pa.lds_stride = geo.rows;
