@@ -62,9 +62,16 @@ static_assert(kLW * kOther == kPanelSlot, "exchange slot sized for the leaf-end 
 // slab stays in global memory (latency of L2), one from LDS.
 template <bool InLds>
 constexpr int kRowUnroll = InLds ? 1 : 2;
+// Resident-leaf variant (one workgroup per matrix, slab in global memory):
+// while a leaf's columns are factored the leaf stays on chip, a thread's
+// rows first + 512 j in registers for j < kResJ and in LDS beyond, so that
+// a column's sweep touches no global memory.  It takes panels of at most
+// kResRows live rows (the LDS part then holds 1024 rows x 16 columns).
+constexpr int kResJ = 3;
+constexpr int kResRows = 2560;
 // Rows per lane step of the leaf-end MFMA reduction (loads issued together).
 template <bool InLds>
-constexpr int kQuadUnroll = InLds ? 2 : 4;
+constexpr int kQuadUnroll = InLds ? 2 : 16;
 // Cache-policy operand of a buffer load that makes it coherent at agent
 // scope (sc1 on gfx950), and the fourth word of a raw buffer resource.
 constexpr int kCoherentLoad = 16;
@@ -83,7 +90,7 @@ struct PanelArgs {
     unsigned seq;                        // exchange x of this panel is published as seq + x + 1
     int* error_flag;
     unsigned spin_limit;
-    int lds_stride;                      // InLds: leading dimension of the slab in LDS
+    int lds_stride;                      // leading dimension of the slab (InLds) or of the leaf's rows (Res) in LDS
 };
 
 // The workgroup's slab (rows [r0, r1) of the panel) lives either in LDS
@@ -92,6 +99,14 @@ struct PanelArgs {
 // One level of the transposing butterfly: lanes with bit OFF set keep the
 // upper HALF of their values, the others the lower, each adding its
 // partner's copy of the kept half (compile-time indices keep h in registers).
+// A wave-uniform double moved to scalar registers.
+__device__ inline double uniform(double x) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 template <int HALF, int OFF>
 __device__ inline void butterfly_step(double (&h)[16], int lane) {
     const bool upper = (lane & OFF) != 0;
@@ -117,8 +132,9 @@ __device__ inline void butterfly_step(double (&h)[16], int lane) {
 // applies the leaf's block reflector to C:  C -= V_s (T_s^T (V_s^T C)).
 // Against one sweep of all 64 columns per column, this sweeps 16 columns per
 // column and the whole panel twice per leaf.
-template <bool InLds>
+template <bool InLds, bool Res = false>
 __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
+    static_assert(!(InLds && Res), "the resident leaf is for slabs in global memory");
     extern __shared__ double smem[];
     __shared__ double s_T[kNB * (kNB + 1) / 2];  // upper T packed by columns: T[i][l] at l (l + 1) / 2 + i
     // Leaf-end sums W[i][q] at i * kOther + q (i: leaf column, q: other
@@ -127,6 +143,7 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
     __shared__ double s_W[kLW * kOther];
     __shared__ double s_coef[kLW], s_z[kLW];
     __shared__ double s_rfl[4];          // beta, tau, scale of the latest reflector
+    __shared__ double s_prow[kLW];       // Res: the pivot row of the leaf after the sweep
     double* const s_wp = s_W;
     const int g = blockIdx.x % a.G, b = blockIdx.x / a.G;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -138,6 +155,10 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
     const int nb = a.nb;
     const long long xld = InLds ? a.lds_stride : ld;
     double* __restrict__ X = InLds ? smem : P + r0;
+    constexpr int S = 64 * kRG;          // row stride of a lane
+    const int first = r0 + 64 * wv + lane;  // this thread's rows: first + S j
+    const int ldl = a.lds_stride;        // Res: LDS rows of the leaf, row first + S (kResJ + j) at 64 w + lane + S j
+    double xr[Res ? kResJ : 1][kLW];     // Res: the leaf on this thread's first kResJ rows
     if (InLds) {
         for (int e = tid; e < (r1 - r0) * nb; e += kPT) {
             const int rl = e % (r1 - r0), j = e / (r1 - r0);
@@ -263,6 +284,21 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
 
     for (int c0 = 0; c0 < nb; c0 += kLW) {
         const int lw = min(kLW, nb - c0);
+        if constexpr (Res) {
+            // The leaf onto the chip (each thread its own rows).
+#pragma unroll
+            for (int j = 0; j < kResJ; ++j) {
+                const int row = first + S * j;
+#pragma unroll
+                for (int q = 0; q < kLW; ++q)
+                    xr[j][q] = row < r1 ? X[row - r0 + (c0 + min(q, lw - 1)) * xld] : 0.0;
+            }
+            for (int row = first + S * kResJ; row < r1; row += S) {
+                const int rr = row - r0 - S * kResJ;
+#pragma unroll
+                for (int q = 0; q < kLW; ++q) smem[rr + q * ldl] = X[row - r0 + (c0 + min(q, lw - 1)) * xld];
+            }
+        }
         for (int kk = 0; kk < lw; ++kk) {
             const int k = c0 + kk;
             // Sweep: reflector k-1 (inside this leaf) on the leaf's columns
@@ -276,7 +312,10 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
             for (int q = 0; q < kLW; ++q) {
                 const double c = s_coef[q];
                 acc[q] = 0.0;
-                cq[q] = (kk > 0 && q > kk && q < lw) ? c : 0.0;
+                // Res: column kk too (its coefficient is ck), so that the
+                // sweep leaves reflector k-1 applied to column kk in place.
+                cq[q] = (kk > 0 && (Res ? q >= kk : q > kk) && q < lw) ? c : 0.0;
+                if constexpr (Res) cq[q] = uniform(cq[q]);  // wave-uniform: scalar registers
             }
             const double ck = kk > 0 ? s_coef[kk] : 0.0;
             const int lo = max(r0, kk > 0 ? k - 1 : k);
@@ -312,14 +351,59 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
                         if (q > kk && q < lw) X[rl + (c0 + q) * xld] = val[q];
                 }
             };
-            constexpr int S = 64 * kRG;  // row stride of a lane
-            const int first = r0 + 64 * wv + lane;
-            for (int row = first; row < r1; row += S * U) {
-                double val[U][kLW], vraw[U], xraw[U];
+            if constexpr (Res) {
+                // The same arithmetic on the resident leaf, with column kk
+                // updated in place; the thread that owns the pivot row
+                // (always a register row) publishes it.
 #pragma unroll
-                for (int u = 0; u < U; ++u) load_row(row + S * u, val[u], vraw[u], xraw[u]);
+                for (int j = 0; j < kResJ; ++j) {
+                    const int row = first + S * j;
+                    if (row >= lo && row < r1) {
+                        double vprev = 0.0;
+                        if (kk > 0) {
+                            double vr = 0.0;
 #pragma unroll
-                for (int u = 0; u < U; ++u) finish_row(row + S * u, val[u], vraw[u], xraw[u]);
+                            for (int q = 0; q < kLW; ++q)
+                                if (q + 1 == kk) vr = xr[j][q];
+                            vprev = row == k - 1 ? 1.0 : vr;
+                        }
+#pragma unroll
+                        for (int q = 0; q < kLW; ++q) xr[j][q] = xr[j][q] - cq[q] * vprev;
+                        double xk = 0.0;
+#pragma unroll
+                        for (int q = 0; q < kLW; ++q)
+                            if (q == kk) xk = xr[j][q];
+                        const double xa = row > k ? xk : 0.0;  // column k below the pivot
+#pragma unroll
+                        for (int q = 0; q < kLW; ++q) acc[q] += xa * xr[j][q];
+                        if (row == k) {
+#pragma unroll
+                            for (int q = 0; q < kLW; ++q) s_prow[q] = xr[j][q];
+                        }
+                    }
+                }
+                for (int row = first + S * kResJ; row < r1; row += S) {
+                    if (row < lo) continue;
+                    // LDS rows column by column (no row copy in registers).
+                    const int rr = row - r0 - S * kResJ;
+                    const double vprev = kk > 0 ? (row == k - 1 ? 1.0 : smem[rr + (kk - 1) * ldl]) : 0.0;
+                    const double xk = smem[rr + kk * ldl] - ck * vprev;
+                    const double xa = row > k ? xk : 0.0;
+#pragma unroll
+                    for (int q = 0; q < kLW; ++q) {
+                        const double v = smem[rr + q * ldl] - cq[q] * vprev;
+                        acc[q] += xa * v;
+                        if (kk > 0 && q >= kk && q < lw) smem[rr + q * ldl] = v;
+                    }
+                }
+            } else {
+                for (int row = first; row < r1; row += S * U) {
+                    double val[U][kLW], vraw[U], xraw[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) load_row(row + S * u, val[u], vraw[u], xraw[u]);
+#pragma unroll
+                    for (int u = 0; u < U; ++u) finish_row(row + S * u, val[u], vraw[u], xraw[u]);
+                }
             }
             {
                 // The 16 column sums of the wave in one transposing butterfly:
@@ -354,8 +438,13 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
                     for (int q = 1; q < kRG; ++q) val += s_wp[q * kLW + lane];
                 } else if (lane < 2 * kLW && k >= r0 && k < r1) {
                     const int q = lane - kLW, rl = k - r0;
-                    double v = X[rl + (c0 + min(q, lw - 1)) * xld];
-                    if (q == kk) v -= ck * (kk > 0 ? X[rl + (k - 1) * xld] : 0.0);
+                    double v;
+                    if constexpr (Res) {
+                        v = s_prow[q];
+                    } else {
+                        v = X[rl + (c0 + min(q, lw - 1)) * xld];
+                        if (q == kk) v -= ck * (kk > 0 ? X[rl + (k - 1) * xld] : 0.0);
+                    }
                     val = q < lw ? v : 0.0;
                 }
                 double sum = val;
@@ -390,12 +479,36 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
             // Column k on this thread's rows: R entry on row k-1, beta on the
             // pivot, v below (column k was not stored by the sweep; column
             // k-1 on these rows was written by this thread).
-            for (int row = first; row < r1; row += S) {
-                if (row < lo) continue;
-                const int rl = row - r0;
-                const double vprev = kk > 0 ? (row == k - 1 ? 1.0 : X[rl + (k - 1) * xld]) : 0.0;
-                const double x = X[rl + k * xld] - ck * vprev;
-                X[rl + k * xld] = row == k ? beta : (row > k ? scale * x : x);
+            if constexpr (Res) {
+                // Column kk already holds reflector k-1's result (the sweep).
+#pragma unroll
+                for (int j = 0; j < kResJ; ++j) {
+                    const int row = first + S * j;
+                    if (row >= lo && row < r1) {
+                        double x = 0.0;
+#pragma unroll
+                        for (int q = 0; q < kLW; ++q)
+                            if (q == kk) x = xr[j][q];
+                        const double nv = row == k ? beta : (row > k ? scale * x : x);
+#pragma unroll
+                        for (int q = 0; q < kLW; ++q)
+                            if (q == kk) xr[j][q] = nv;
+                    }
+                }
+                for (int row = first + S * kResJ; row < r1; row += S) {
+                    if (row < lo) continue;
+                    const int rr = row - r0 - S * kResJ;
+                    const double x = smem[rr + kk * ldl];
+                    smem[rr + kk * ldl] = row == k ? beta : (row > k ? scale * x : x);
+                }
+            } else {
+                for (int row = first; row < r1; row += S) {
+                    if (row < lo) continue;
+                    const int rl = row - r0;
+                    const double vprev = kk > 0 ? (row == k - 1 ? 1.0 : X[rl + (k - 1) * xld]) : 0.0;
+                    const double x = X[rl + k * xld] - ck * vprev;
+                    X[rl + k * xld] = row == k ? beta : (row > k ? scale * x : x);
+                }
             }
             // Column kk of the leaf's T_s (every workgroup keeps T_s):
             // T[c0+j][k] = -tau sum_l T[c0+j][c0+l] z_l, T[k][k] = tau.
@@ -418,6 +531,24 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
                 }
             }
         }
+        if constexpr (Res) {
+            // The leaf back to global memory (each thread its own rows).
+#pragma unroll
+            for (int j = 0; j < kResJ; ++j) {
+                const int row = first + S * j;
+                if (row < r1) {
+#pragma unroll
+                    for (int q = 0; q < kLW; ++q)
+                        if (q < lw) X[row - r0 + (c0 + q) * xld] = xr[j][q];
+                }
+            }
+            for (int row = first + S * kResJ; row < r1; row += S) {
+                const int rr = row - r0 - S * kResJ;
+#pragma unroll
+                for (int q = 0; q < kLW; ++q)
+                    if (q < lw) X[row - r0 + (c0 + q) * xld] = smem[rr + q * ldl];
+            }
+        }
         __syncthreads();  // the leaf's columns and T_s are complete
 
         // Leaf end: W = V_s^T [V_prev, C] over rows >= c0 (V_s is zero above
@@ -428,16 +559,19 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
         if (nother == 0) break;
         const int nblk = (nother + 15) / 16;
         const int rs = max(r0, c0);
-        if (wv < nblk) {
-            const int q0 = wv * 16;
+        // Wave w takes block w % nblk over every nparts-th group of rows
+        // (part w / nblk); the parts' blocks are added in part order.
+        const int nparts = kRG / nblk;
+        const int part = wv / nblk;
+        d4 w4 = d4{0, 0, 0, 0};
+        const int q0 = (wv % nblk) * 16;
+        const int i = lane & 15;
+        if (part < nparts) {
             const int cb = q0 < c0 ? q0 : q0 + lw;  // first column of the block (blocks do not straddle the leaf)
-            const int i = lane & 15;
             const int ci = c0 + i, cj = cb + i;
             const bool iok = i < lw, jok = cj < nb && (q0 + i) < nother;
-            d4 w4 = d4{0, 0, 0, 0};
             constexpr int UQ = kQuadUnroll<InLds>;
-            int base = rs;
-            for (; base < r1; base += 4 * UQ) {
+            for (int base = rs + 4 * UQ * part; base < r1; base += 4 * UQ * nparts) {
                 double av[UQ], bv[UQ];
 #pragma unroll
                 for (int u = 0; u < UQ; ++u) {
@@ -452,13 +586,18 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
 #pragma unroll
                 for (int u = 0; u < UQ; ++u) w4 = mfma_f64_16x16x4(av[u], bv[u], w4);
             }
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int ii = Mfma<double>::row(lane, e);
-                s_W[ii * kOther + q0 + i] = w4[e];
-            }
         }
-        __syncthreads();
+        for (int pp = 0; pp < nparts; ++pp) {
+            if (part == pp) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int ii = Mfma<double>::row(lane, e);
+                    double& d = s_W[ii * kOther + q0 + i];
+                    d = pp == 0 ? w4[e] : d + w4[e];
+                }
+            }
+            __syncthreads();
+        }
         exchange(s_W, s_W, lw * kOther);
 
         if (g == 0 && c0 > 0) {
@@ -505,10 +644,12 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
                 }
             }
             __syncthreads();
+            // W2 goes back transposed, W2[i][q] at q * kLW + i (q: column of
+            // C), so that a column's 16 entries are contiguous.
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int t = tid + h * kPT;
-                if (t < lw * nc) s_W[(t / nc) * kOther + c0 + t % nc] = m[h];
+                if (t < lw * nc) s_W[(t % nc) * kLW + t / nc] = m[h];
             }
             __syncthreads();
             for (int r = rs + tid; r < r1; r += kPT) {
@@ -520,12 +661,21 @@ __global__ __launch_bounds__(kPT) void panel_kernel(PanelArgs a) {
                     const double x = X[rl + min(ci, nb - 1) * xld];
                     v[i] = (i < lw && r >= ci) ? (r == ci ? 1.0 : x) : 0.0;
                 }
-                for (int q = 0; q < nc; ++q) {
-                    const int col = c0 + lw + q;
-                    double s = 0.0;
+                // Sixteen columns' loads issued together.
+#pragma unroll 1
+                for (int q0 = 0; q0 < nc; q0 += 16) {
+                    double cv[16];
 #pragma unroll
-                    for (int i = 0; i < kLW; ++i) s += v[i] * s_W[i * kOther + c0 + q];
-                    X[rl + col * xld] -= s;
+                    for (int u = 0; u < 16; ++u) cv[u] = q0 + u < nc ? X[rl + (c0 + lw + q0 + u) * xld] : 0.0;
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) {
+                        if (q0 + u < nc) {
+                            double s = 0.0;
+#pragma unroll
+                            for (int i = 0; i < kLW; ++i) s += v[i] * s_W[(q0 + u) * kLW + i];
+                            X[rl + (c0 + lw + q0 + u) * xld] = cv[u] - s;
+                        }
+                    }
                 }
             }
         }
@@ -620,13 +770,16 @@ constexpr int kPanelRowsTarget = 256;
 // 3.34 s with cooperative panels, 2.81 s with single-workgroup panels.
 constexpr int kSinglePanelRows = 2304;
 
-constexpr int kStaticLds = (kNB * (kNB + 1) / 2 + kLW * kOther + 4 * kLW) * 8 + 256;
+constexpr int kStaticLds = (kNB * (kNB + 1) / 2 + kLW * kOther + 5 * kLW) * 8 + 256;
 
 int lds_limit() {
     static int v = [] {
         int dev = 0, bytes = 0;
         if (hipGetDevice(&dev) != hipSuccess) return 0;
         if (hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 0;
+        if (hipFuncSetAttribute((const void*)panel_kernel<false, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                bytes - kStaticLds) != hipSuccess)
+            return 0;
         if (hipFuncSetAttribute((const void*)panel_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 bytes - kStaticLds) != hipSuccess)
             return 0;
@@ -777,11 +930,18 @@ hipError_t run_panel(int m, int e, int p, int nb, double* M, long long ld, long 
     hipError_t err;
     if (geo.G == 1) {
         // One workgroup per matrix needs no co-residency: an ordinary launch
-        // on the solve's own stream, free to overlap other solves.
-        StatScope sc(geo.lds ? "panel_kernel<lds>" : "panel_kernel<global>", st, 4.0 * L * (double)nb * nb * batch,
-                     16.0 * L * (double)nb * batch);
+        // on the solve's own stream, free to overlap other solves.  A slab
+        // that the LDS does not hold keeps each leaf on chip while it is
+        // factored when it has at most kResRows rows.
+        const bool res = !geo.lds && L <= kResRows && lds_limit() > 0;
+        const int res_rows = std::max(L - kPT * kResJ, 0);
+        if (res) pa.lds_stride = std::max(res_rows, 1);
+        StatScope sc(geo.lds ? "panel_kernel<lds>" : (res ? "panel_kernel<resident>" : "panel_kernel<global>"), st,
+                     4.0 * L * (double)nb * nb * batch, 16.0 * L * (double)nb * batch);
         if (geo.lds)
             panel_kernel<true><<<batch, kPT, (size_t)geo.rows * kNB * sizeof(double), st>>>(pa);
+        else if (res)
+            panel_kernel<false, true><<<batch, kPT, (size_t)res_rows * kLW * sizeof(double), st>>>(pa);
         else
             panel_kernel<false><<<batch, kPT, 0, st>>>(pa);
         sc.end();
