@@ -368,9 +368,29 @@ def bench_batched(args):
     fl = sum(inf["flops_paper"] for inf in infos)
     # accuracy on a sample of the batch
     errs = []
-    for i in range(0, len(mats), max(1, len(mats) // 16)):
+    sample = list(range(0, len(mats), max(1, len(mats) // 16)))
+    for i in sample:
         _, _, inf = z.pd(mats[i], alpha=1.0, l=ls[i], compute_errors=1)
         errs.append((inf["bwd_err"], inf["orth_err"]))
+    # The mixed form of the same call beside it (FP32 only for Cholesky-type
+    # steps that are not predicted to be the last one), with its errors on
+    # the same sample.
+    z.pd_batched(mats, alphas=[1.0] * len(mats), ls=ls, batch_streams=args.batch_streams, precision=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, minfos = z.pd_batched(mats, alphas=[1.0] * len(mats), ls=ls, batch_streams=args.batch_streams,
+                                precision=1)
+    torch.cuda.synchronize()
+    dt_mixed = time.perf_counter() - t0
+    merrs = []
+    for i in sample:
+        _, _, inf = z.pd(mats[i], alpha=1.0, l=ls[i], compute_errors=1, precision=1)
+        merrs.append((inf["bwd_err"], inf["orth_err"]))
+    steps = "".join(inf["prec"] for inf in minfos)
+    mixed = {"ms": dt_mixed * 1e3, "value": sum(inf["flops_paper"] for inf in minfos) / dt_mixed / 1e12,
+             "fp32_steps": steps.count("s"), "steps": len(steps),
+             "max_bwd_err_sampled": max(e[0] for e in merrs), "max_orth_err_sampled": max(e[1] for e in merrs),
+             "not_converged": sum(1 for i in minfos if i["status"] != 0)}
     out = {"metric": "Zolo-PD batched throughput (uneven matrices)", "value": fl / dt / 1e12, "unit": "TFLOP/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
@@ -382,7 +402,7 @@ def bench_batched(args):
            "r_histogram": {str(k): sum(1 for i in infos if i["r"] == k) for k in range(1, 9)},
            "max_bwd_err_sampled": max(e[0] for e in errs), "max_orth_err_sampled": max(e[1] for e in errs),
            "not_converged": sum(1 for i in infos if i["status"] != 0), "roofline": roof,
-           "kernels_busy_ms": kernels}
+           "kernels_busy_ms": kernels, "mixed": mixed}
     print(json.dumps(out), flush=True)
     z.close()
 
