@@ -242,9 +242,10 @@ def test_batched_uneven(z):
 
 
 def test_batched_mid_sizes(z):
-    # Matrices of the 512-matrix uneven workload with n = 600..1000 (panels
-    # spread over 10-18 workgroups each), solved in one batched call.  Exact
-    # H = V diag(sigma) V^T is known from the construction.
+    # Matrices of the 512-matrix uneven workload with n = 600..1000 (one
+    # workgroup per panel, the leaf held in registers and LDS), solved in one
+    # batched call.  Exact H = V diag(sigma) V^T is known from the
+    # construction.
     specs = W.batch_specs(count=512, seed=4000)
     pick = [specs[i] for i in (127, 143, 195, 268)]
     built = [W.svd_matrix(sp["m"], sp["n"], sp["kappa"], sp["seed_u"], sp["seed_v"]) for sp in pick]
@@ -256,6 +257,27 @@ def test_batched_mid_sizes(z):
         assert oz.backward_error(A, Q, H) <= BAR and oz.orthogonality(Q) <= BAR
         Hx = (V * sig) @ V.T
         assert np.linalg.norm(H - Hx) / np.linalg.norm(Hx) <= 1e-12
+
+
+def test_batched_resident_leaf_boundaries(z):
+    # Single-workgroup panels of the many-matrix call keep a thread's first
+    # 3 rows (1536 rows in all) of each 16-column leaf in registers and the
+    # rest in LDS.  Live rows m + 64 just below, at and above that boundary,
+    # at the 2304-row limit of single-workgroup panels, with a ragged last
+    # leaf (n = 40) and a ragged second panel (n = 70), against the oracle.
+    cases = [(1471, 40, 1e6), (1472, 70, 1e9), (1473, 40, 1e4), (2240, 70, 1e6)]
+    from oracle import coeffs as oc
+    mats = [W.svd_matrix(m, n, kappa, 50 + m, 60 + n)[0] for m, n, kappa in cases]
+    ls = [1.0 / kappa for _, _, kappa in cases]
+    rs = [oc.choose_r(l) for l in ls]
+    Qs, Hs, infos = z.pd_batched([dev(A) for A in mats], alphas=[1.0] * len(mats), ls=ls, rs=rs)
+    for A, Q, H, inf, l, r in zip(mats, Qs, Hs, infos, ls, rs):
+        Q, H = Q.cpu().numpy(), H.cpu().numpy()
+        Qo, Ho, io = oz.zolo_pd(A, 1.0, l, r)
+        assert inf["status"] == 0, inf
+        same_schedule(inf, io)
+        assert oz.backward_error(A, Q, H) <= BAR and oz.orthogonality(Q) <= BAR
+        assert np.linalg.norm(H - Ho) / np.linalg.norm(Ho) <= 1e-12
 
 
 def test_mixed_schedule_fp32_middle_step(z):
