@@ -750,8 +750,18 @@ __global__ __launch_bounds__(256, 2) void dgemm_dma_kernel(GemmDescT<double> d) 
     using LA = Lay<BM, TA>;
     using LB = Lay<BN, !TB>;
     constexpr int NA = LA::kChunks * 2, NB = LB::kChunks * 2;   // doubles per slice
-    __shared__ __align__(16) double As0[NA], As1[NA], As2[NA];
-    __shared__ __align__(16) double Bs0[NB], Bs1[NB], Bs2[NB];
+    // Three LDS stages of A and B slices; after the k-loop the same memory
+    // holds the output tile for the coalesced epilogue.
+    __shared__ __align__(16) double lds[3 * (NA + NB)];
+    double* const As0 = lds;
+    double* const As1 = lds + NA;
+    double* const As2 = lds + 2 * NA;
+    double* const Bs0 = lds + 3 * NA;
+    double* const Bs1 = lds + 3 * NA + NB;
+    double* const Bs2 = lds + 3 * NA + 2 * NB;
+    // Output tile in LDS, column-major with a padded leading dimension.
+    constexpr int TLD = BM + 2;
+    static_assert(BN * TLD <= 3 * (NA + NB), "the output tile fits in the stage buffers");
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wv = __builtin_amdgcn_readfirstlane(wave);
@@ -801,19 +811,21 @@ __global__ __launch_bounds__(256, 2) void dgemm_dma_kernel(GemmDescT<double> d) 
     const double* Cin = d.Cin ? d.Cin + (long long)ob * d.strideCin + (long long)z2 * d.strideCin2 : nullptr;
     const double alpha = d.alpha, beta = d.beta;
     const bool use_cin = !split && Cin != nullptr && d.beta != 0.0;
-    double cin[FM][FN][4];
+    // Cin in the coalesced layout of the epilogue: wave w takes the tile's
+    // columns w, w + 4, ..., lane l its rows l, l + 64, ...; each load
+    // instruction reads one column segment of 64 rows.
+    constexpr int CPW = BN / 4, RPL = BM / 64;
+    double cin[CPW][RPL];
     auto load_cin = [&]() __attribute__((always_inline)) {
 #pragma unroll
-        for (int i = 0; i < FM; ++i)
+        for (int q = 0; q < CPW; ++q)
 #pragma unroll
-            for (int j = 0; j < FN; ++j)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int gi = row0 + wm + i * 16 + Mfma<double>::row(lane, e);
-                    const int gj = col0 + wn + j * 16 + (lane & 15);
-                    const bool ok = gi < d.m && gj < d.n;
-                    cin[i][j][e] = Cin[ok ? gi + (long long)gj * d.ldcin : 0];
-                }
+            for (int u = 0; u < RPL; ++u) {
+                const int gi = row0 + lane + 64 * u;
+                const int gj = col0 + wv + 4 * q;
+                const bool ok = gi < d.m && gj < d.n;
+                cin[q][u] = Cin[ok ? gi + (long long)gj * d.ldcin : 0];
+            }
     };
     if (PRE && use_cin) load_cin();
 
@@ -995,40 +1007,51 @@ __global__ __launch_bounds__(256, 2) void dgemm_dma_kernel(GemmDescT<double> d) 
         }
     }
 
+    // Split-K pieces store their partial sums as they are (m x n, column-major)
+    // through the same coalesced epilogue.
+    double* __restrict__ Out = C;
+    long long ldo = d.ldc;
+    double alo = alpha;
+    unsigned sfl = fl;
     if (split) {
         const int nout = d.reduce ? 1 : d.batch;
-        double* __restrict__ Wp = d.work + ((long long)blockIdx.z * nout + ob) * ((long long)d.m * d.n);
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-            for (int j = 0; j < FN; ++j)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int gi = row0 + wm + i * 16 + Mfma<double>::row(lane, e);
-                    const int gj = col0 + wn + j * 16 + (lane & 15);
-                    if (gi < d.m && gj < d.n) Wp[gi + (long long)gj * d.m] = acc[i][j][e];
-                }
-        return;
+        Out = d.work + ((long long)blockIdx.z * nout + ob) * ((long long)d.m * d.n);
+        ldo = d.m;
+        alo = 1.0;
+        sfl = 0;
     }
     // All Cin loads are issued before the first store (Cin and C may alias).
     if (!PRE && use_cin) load_cin();
+    // The accumulators go through LDS (the stage buffers, once every wave has
+    // finished its last slice) so that each store instruction writes one
+    // column segment of 64 rows instead of sixteen 4-row pieces.
+    __syncthreads();
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int gi = row0 + wm + i * 16 + Mfma<double>::row(lane, e);
-                const int gj = col0 + wn + j * 16 + (lane & 15);
-                bool ok = gi < d.m && gj < d.n;
-                if (fl & kCStoreUpper) ok = ok && gi <= gj;
-                if (fl & kCStoreLower) ok = ok && gi >= gj;
-                if (ok) {
-                    double v = alpha * acc[i][j][e];
-                    if (use_cin) v += beta * cin[i][j][e];
-                    C[gi + (long long)gj * d.ldc] = v;
-                }
+                const int r = wm + i * 16 + Mfma<double>::row(lane, e);
+                const int c = wn + j * 16 + (lane & 15);
+                lds[c * TLD + r] = acc[i][j][e];
             }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < CPW; ++q)
+#pragma unroll
+        for (int u = 0; u < RPL; ++u) {
+            const int r = lane + 64 * u, c = wv + 4 * q;
+            const int gi = row0 + r, gj = col0 + c;
+            bool ok = gi < d.m && gj < d.n;
+            if (sfl & kCStoreUpper) ok = ok && gi <= gj;
+            if (sfl & kCStoreLower) ok = ok && gi >= gj;
+            if (ok) {
+                double v = alo * lds[c * TLD + r];
+                if (use_cin) v += beta * cin[q][u];
+                Out[gi + (long long)gj * ldo] = v;
+            }
+        }
 }
 
 template <int BM, int BN>
