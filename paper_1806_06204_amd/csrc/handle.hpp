@@ -29,4 +29,8 @@ struct zolo_handle_s {
     // panels.
     std::vector<zolo_handle_s*> workers;
     hipStream_t worker_panel_stream = nullptr;
+    // Second stream of the QR look-ahead (structured_geqrf), created by the
+    // first zolo_pd call (never by zolo_pd_noalloc), with its two events.
+    hipStream_t side_stream = nullptr;
+    hipEvent_t ev_side_ready = nullptr, ev_side_done = nullptr;
 };

@@ -76,6 +76,14 @@ struct QrWork {
     size_t splitk_elems = 0;
     hipStream_t panel_stream = nullptr;        // non-null: launch panels there (see run_panel)
     hipEvent_t ev_ready = nullptr, ev_done = nullptr;
+    // Look-ahead (see structured_geqrf): a second stream for the far part of
+    // each trailing update, with buffers of its own (batch 1 sizes).
+    hipStream_t side_stream = nullptr;
+    hipEvent_t ev_side_ready = nullptr, ev_side_done = nullptr;
+    double* W_side = nullptr;     // qr_w_elems(n, 1) doubles
+    double* W2_side = nullptr;    // qr_w_elems(n, 1) doubles
+    double* splitk_side = nullptr;  // qr_split_elems(n, 1) doubles
+    size_t splitk_side_elems = 0;
     bool single_panels = false;   // one workgroup per matrix for panels of few rows (see run_panel)
     double* Rd = nullptr;         // batch * npanels * kPanelNB^2 doubles (R diagonal blocks)
     double* S = nullptr;          // qr_s_elems(batch) doubles

@@ -977,13 +977,13 @@ hipError_t run_panel(int m, int e, int p, int nb, double* M, long long ld, long 
 // the live rows [c0, c0 + L).  T (ld ldt, batch stride stt) is upper
 // triangular.  V's zeros above its unit diagonal, including an R block stored
 // there by an earlier panel of the same block, are masked by the GEMM's
-// triangular flags.
+// triangular flags.  col_off skips that many columns of C first.
 hipError_t apply_block(int L, int c0, int nbv, int trail, const double* Tm, long long ldt, long long stt,
                        bool transpose_t, double* M, long long ld, long long sm, int batch, const QrWork& w,
-                       hipStream_t st) {
+                       hipStream_t st, int col_off = 0) {
     if (trail <= 0) return hipSuccess;
     const double* V = M + c0 + (long long)c0 * ld;
-    double* C = M + c0 + (long long)(c0 + nbv) * ld;
+    double* C = M + c0 + (long long)(c0 + nbv + col_off) * ld;
     const long long sw = (long long)kQrSuper * trail;
     GemmDesc g1;  // W = V^T C
     g1.m = nbv; g1.n = trail; g1.k = L; g1.transa = 1;
@@ -1069,7 +1069,14 @@ hipError_t merge_wy(int m, int e, int c1, int n1, const double* T1, long long ld
 // into 256-column superblocks (factor Ts).  Inside a superblock each block's
 // reflectors update the superblock's remaining columns; the rest of the
 // matrix takes one rank-256 block-reflector update per superblock, so the
-// trailing matrix is read and written once per 256 columns.
+// trailing matrix is read and written once per 256 columns.  That update
+// is done in two parts: the next superblock's 256 columns first, then the
+// far columns.  With one matrix per launch (whose panels leave most of the
+// GPU idle) and a second stream, the far part runs there while the next
+// superblock's panels and inner updates proceed on the caller's stream
+// (look-ahead); the next superblock's own trailing update waits for it.
+// Both orders compute the same products in the same way (the same two
+// column ranges), so the results do not depend on the stream.
 hipError_t structured_geqrf(int m, int e, int n, double* M, long long ld, long long sm, int batch, const QrWork& w,
                             hipStream_t st) {
     if (batch > kMaxInlineAlpha || batch < 1) return hipErrorInvalidValue;
@@ -1081,6 +1088,10 @@ hipError_t structured_geqrf(int m, int e, int n, double* M, long long ld, long l
     const long long sts = (long long)nsuper * kQrSuper * kQrSuper;
     hipError_t err = zero_ints(reinterpret_cast<int*>(w.flags), (int)w.flag_elems, st);
     if (err != hipSuccess) return err;
+    const bool lookahead = batch == 1 && !w.single_panels && w.side_stream && w.side_stream != st &&
+                           w.ev_side_ready && w.ev_side_done && w.W_side && w.W2_side && w.splitk_side &&
+                           (size_t)kQrSuper * n <= qr_w_elems(n, 1);
+    bool side_pending = false;
     for (int Q = 0; Q < nsuper; ++Q) {
         const int s0 = Q * kQrSuper;
         const int nsq = n - s0 < kQrSuper ? n - s0 : kQrSuper, send = s0 + nsq;
@@ -1121,10 +1132,36 @@ hipError_t structured_geqrf(int m, int e, int n, double* M, long long ld, long l
         err = merge_wy(m, e, s0, kQrBlock, TA, kQrBlock, stb, nB, TB, ldB, stB, M, ld, sm, batch, w, Ts, kQrSuper, sts,
                        st);
         if (err != hipSuccess) return err;
-        err = apply_block(live_rows(m, e, s0, nsq), s0, nsq, trail_s, Ts, kQrSuper, sts, true, M, ld, sm, batch, w,
-                          st);
+        // Columns the far part of the previous superblock's update wrote are
+        // read from here on.
+        if (side_pending) {
+            if ((err = hipStreamWaitEvent(st, w.ev_side_done, 0)) != hipSuccess) return err;
+            side_pending = false;
+        }
+        const int L = live_rows(m, e, s0, nsq);
+        const int ahead = trail_s < kQrSuper ? trail_s : kQrSuper;
+        err = apply_block(L, s0, nsq, ahead, Ts, kQrSuper, sts, true, M, ld, sm, batch, w, st);
         if (err != hipSuccess) return err;
+        const int far = trail_s - ahead;
+        if (far <= 0) continue;
+        if (lookahead) {
+            QrWork ws = w;
+            ws.W = w.W_side;
+            ws.W2 = w.W2_side;
+            ws.splitk = w.splitk_side;
+            ws.splitk_elems = w.splitk_side_elems;
+            if ((err = hipEventRecord(w.ev_side_ready, st)) != hipSuccess) return err;
+            if ((err = hipStreamWaitEvent(w.side_stream, w.ev_side_ready, 0)) != hipSuccess) return err;
+            err = apply_block(L, s0, nsq, far, Ts, kQrSuper, sts, true, M, ld, sm, batch, ws, w.side_stream, ahead);
+            if (err != hipSuccess) return err;
+            if ((err = hipEventRecord(w.ev_side_done, w.side_stream)) != hipSuccess) return err;
+            side_pending = true;
+        } else {
+            err = apply_block(L, s0, nsq, far, Ts, kQrSuper, sts, true, M, ld, sm, batch, w, st, ahead);
+            if (err != hipSuccess) return err;
+        }
     }
+    if (side_pending) return hipStreamWaitEvent(st, w.ev_side_done, 0);
     return hipSuccess;
 }
 

@@ -115,6 +115,10 @@ Work layout(char* base, int m, int n, int rmax, int panel_coresident, bool mixed
     w.qr.Ts = ar.take<double>(qr_ts_elems(n, rmax));
     w.qr.splitk = ar.take<double>(qr_split_elems(n, rmax));
     w.qr.splitk_elems = qr_split_elems(n, rmax);
+    w.qr.W_side = ar.take<double>(qr_w_elems(n, 1));
+    w.qr.W2_side = ar.take<double>(qr_w_elems(n, 1));
+    w.qr.splitk_side = ar.take<double>(qr_split_elems(n, 1));
+    w.qr.splitk_side_elems = qr_split_elems(n, 1);
     w.qr.panel_stream = nullptr;
     w.qr.Rd = ar.take<double>((size_t)rmax * npanels * kPanelNB * kPanelNB);
     w.qr.S = ar.take<double>(qr_s_elems(rmax));
@@ -450,6 +454,9 @@ int pd_core(zolo_handle h, char* base, int m, int n, const double* A, int lda, d
     w.qr.single_panels = h->single_panels;
     w.qr.ev_ready = h->ev_ready;
     w.qr.ev_done = h->ev_done;
+    w.qr.side_stream = h->side_stream;
+    w.qr.ev_side_ready = h->ev_side_ready;
+    w.qr.ev_side_done = h->ev_side_done;
     hipStream_t st = h->stream;
     int* hi = reinterpret_cast<int*>(h->host);
     int rc = 0;
@@ -717,6 +724,12 @@ int zolo_destroy(zolo_handle h) {
     if (!h) return -1;
     (void)hipStreamSynchronize(h->stream);
     release_workers(h);
+    if (h->side_stream) {
+        (void)hipStreamSynchronize(h->side_stream);
+        (void)hipEventDestroy(h->ev_side_ready);
+        (void)hipEventDestroy(h->ev_side_done);
+        (void)hipStreamDestroy(h->side_stream);
+    }
     if (h->arena) (void)hipFree(h->arena);
     if (h->host) (void)hipHostFree(h->host);
     if (h->est) (void)hipFree(h->est);
@@ -750,6 +763,27 @@ int zolo_predict(double l, int r, int m, int n, double chol_switch, char* kinds,
     return 0;
 }
 
+// The QR look-ahead's stream and events (non-blocking, default priority);
+// without them the look-ahead's two parts run on the caller's stream.
+static void ensure_side_stream(zolo_handle h) {
+    if (h->side_stream) return;
+    hipStream_t s = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return;
+    if (hipEventCreateWithFlags(&a, hipEventDisableTiming) != hipSuccess) {
+        (void)hipStreamDestroy(s);
+        return;
+    }
+    if (hipEventCreateWithFlags(&b, hipEventDisableTiming) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        (void)hipStreamDestroy(s);
+        return;
+    }
+    h->side_stream = s;
+    h->ev_side_ready = a;
+    h->ev_side_done = b;
+}
+
 int zolo_pd(zolo_handle h, int m, int n, const double* A, int lda, double alpha, double l, int r, double* Qp,
             int ldq, double* H, int ldh, const zolo_opts* opts_in, zolo_info* info) {
     zolo_opts opts;
@@ -757,6 +791,7 @@ int zolo_pd(zolo_handle h, int m, int n, const double* A, int lda, double alpha,
     if (rc) return report(info, rc);
     const size_t bytes = workspace_bytes(h, m, n, r, opts);
     if ((rc = ensure(h, bytes))) return report(info, rc);
+    ensure_side_stream(h);
     return pd_core(h, h->arena, m, n, A, lda, alpha, l, r, Qp, ldq, H, ldh, opts, info);
 }
 
