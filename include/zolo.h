@@ -22,6 +22,11 @@
  *     overlap A;
  *   - the library owns its device workspace, kept in the handle and grown on
  *     demand; zolo_destroy releases it;
+ *   - zolo_pd's QR-type steps of one matrix (r = 1, and the condition
+ *     estimate) also queue part of each trailing update on a second stream
+ *     that the handle creates on its first zolo_pd call, ordered against the
+ *     handle's stream by events; everything is complete when the call
+ *     returns, and the results are the same as on one stream;
  *   - no call prints, throws or aborts.
  *
  * Return codes (int):
