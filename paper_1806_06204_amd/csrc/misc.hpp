@@ -82,7 +82,7 @@ struct QrWork {
     hipEvent_t ev_side_ready = nullptr, ev_side_done = nullptr;
     double* W_side = nullptr;     // qr_w_elems(n, 1) doubles
     double* W2_side = nullptr;    // qr_w_elems(n, 1) doubles
-    double* splitk_side = nullptr;  // qr_split_elems(n, 1) doubles
+    double* splitk_side = nullptr;  // 4 qr_w_elems(n, 1) doubles
     size_t splitk_side_elems = 0;
     bool single_panels = false;   // one workgroup per matrix for panels of few rows (see run_panel)
     double* Rd = nullptr;         // batch * npanels * kPanelNB^2 doubles (R diagonal blocks)

@@ -1144,12 +1144,16 @@ hipError_t structured_geqrf(int m, int e, int n, double* M, long long ld, long l
         if (err != hipSuccess) return err;
         const int far = trail_s - ahead;
         if (far <= 0) continue;
-        if (lookahead) {
-            QrWork ws = w;
+        // One matrix: the far part runs on the side buffers (batch 1 sizes)
+        // on either stream, since its split-K depends on the buffer size.
+        QrWork ws = w;
+        if (batch == 1 && w.W_side && w.W2_side && w.splitk_side) {
             ws.W = w.W_side;
             ws.W2 = w.W2_side;
             ws.splitk = w.splitk_side;
             ws.splitk_elems = w.splitk_side_elems;
+        }
+        if (lookahead) {
             if ((err = hipEventRecord(w.ev_side_ready, st)) != hipSuccess) return err;
             if ((err = hipStreamWaitEvent(w.side_stream, w.ev_side_ready, 0)) != hipSuccess) return err;
             err = apply_block(L, s0, nsq, far, Ts, kQrSuper, sts, true, M, ld, sm, batch, ws, w.side_stream, ahead);
@@ -1157,7 +1161,7 @@ hipError_t structured_geqrf(int m, int e, int n, double* M, long long ld, long l
             if ((err = hipEventRecord(w.ev_side_done, w.side_stream)) != hipSuccess) return err;
             side_pending = true;
         } else {
-            err = apply_block(L, s0, nsq, far, Ts, kQrSuper, sts, true, M, ld, sm, batch, w, st, ahead);
+            err = apply_block(L, s0, nsq, far, Ts, kQrSuper, sts, true, M, ld, sm, batch, ws, st, ahead);
             if (err != hipSuccess) return err;
         }
     }

@@ -117,8 +117,8 @@ Work layout(char* base, int m, int n, int rmax, int panel_coresident, bool mixed
     w.qr.splitk_elems = qr_split_elems(n, rmax);
     w.qr.W_side = ar.take<double>(qr_w_elems(n, 1));
     w.qr.W2_side = ar.take<double>(qr_w_elems(n, 1));
-    w.qr.splitk_side = ar.take<double>(qr_split_elems(n, 1));
-    w.qr.splitk_side_elems = qr_split_elems(n, 1);
+    w.qr.splitk_side = ar.take<double>(4 * qr_w_elems(n, 1));
+    w.qr.splitk_side_elems = 4 * qr_w_elems(n, 1);
     w.qr.panel_stream = nullptr;
     w.qr.Rd = ar.take<double>((size_t)rmax * npanels * kPanelNB * kPanelNB);
     w.qr.S = ar.take<double>(qr_s_elems(rmax));

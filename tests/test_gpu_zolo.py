@@ -287,24 +287,27 @@ def test_lookahead_same_bits(z):
     # whose first call is the allocation-free entry point has no second
     # stream: both give the same bits, and H matches the exact
     # V diag(sigma) V^T.  n = 700 has three superblocks, so far parts exist.
+    # The second case leaves r to the least-predicted-time policy (one
+    # matrix per factorisation only if the policy picks r = 1).
     from paper_1806_06204_amd import zolo
     m, n, kappa = 1100, 700, 1e12
     A, U, sig, V = W.svd_matrix(m, n, kappa, 81, 82)
     Ad = zolo.to_device(A)
-    fresh = zolo.Zolo()
-    try:
-        Qa, Ha, ia = fresh.pd(Ad, alpha=1.0, l=1.0 / kappa, r=1, noalloc=True)
-        Qa, Ha = Qa.cpu().numpy(), Ha.cpu().numpy()
-    finally:
-        fresh.close()
-    Qb, Hb, ib = z.pd(Ad, alpha=1.0, l=1.0 / kappa, r=1)
-    Qb, Hb = Qb.cpu().numpy(), Hb.cpu().numpy()
-    assert ia["status"] == 0 and ib["status"] == 0 and ia["kinds"] == ib["kinds"]
-    assert ia["kinds"][:2] == ["Q", "Q"]
-    assert np.array_equal(Qa, Qb) and np.array_equal(Ha, Hb)
-    assert oz.backward_error(A, Qb, Hb) <= BAR and oz.orthogonality(Qb) <= BAR
     Hx = (V * sig) @ V.T
-    assert np.linalg.norm(Hb - Hx) / np.linalg.norm(Hx) <= 1e-12
+    for kw in ({"r": 1}, {"r": None, "r_policy": 1}):
+        fresh = zolo.Zolo()
+        try:
+            Qa, Ha, ia = fresh.pd(Ad, alpha=1.0, l=1.0 / kappa, noalloc=True, **kw)
+            Qa, Ha = Qa.cpu().numpy(), Ha.cpu().numpy()
+        finally:
+            fresh.close()
+        Qb, Hb, ib = z.pd(Ad, alpha=1.0, l=1.0 / kappa, **kw)
+        Qb, Hb = Qb.cpu().numpy(), Hb.cpu().numpy()
+        assert ia["status"] == 0 and ib["status"] == 0 and ia["kinds"] == ib["kinds"], kw
+        assert ia["r"] == ib["r"] and ia["kinds"][0] == "Q", (kw, ia["r"], ia["kinds"])
+        assert np.array_equal(Qa, Qb) and np.array_equal(Ha, Hb), kw
+        assert oz.backward_error(A, Qb, Hb) <= BAR and oz.orthogonality(Qb) <= BAR
+        assert np.linalg.norm(Hb - Hx) / np.linalg.norm(Hx) <= 1e-12
 
 
 def test_mixed_schedule_fp32_middle_step(z):
