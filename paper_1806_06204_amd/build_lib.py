@@ -20,11 +20,17 @@ ARCH = "--offload-arch=gfx950"
 # Packed FP32 instructions are switched off for all device code.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function"]
+# Per-file options.  gemm.hip: MFMA accumulators in ordinary VGPRs.  Kernels
+# allowed more than 256 registers per lane (the 128 x 128 tiles, one
+# workgroup per CU) otherwise get the accumulator-register form of the MFMA,
+# and the compiler copies all accumulators in and out of those registers
+# around every k-slice.
+FILE_FLAGS = {"gemm.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _compile(src):
     obj = os.path.join(BUILD, src + ".o")
-    cmd = [HIPCC, ARCH, *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, ARCH, *COMMON, *FILE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".hip"):
         cmd[2:2] = DEVICE_FLAGS
         cmd.insert(1, "-xhip")

@@ -744,7 +744,7 @@ __device__ inline unsigned lds_addr(const void* p) {
 // PRE: load the Cin tile before the k-loop (short k-ranges, where its
 // latency would not hide behind the loop); otherwise after it.
 template <int BM, int BN, bool TA, bool TB, bool PRE>
-__global__ __launch_bounds__(256, 2) void dgemm_dma_kernel(GemmDescT<double> d) {
+__global__ __launch_bounds__(256, BM * BN >= 128 * 128 ? 1 : 2) void dgemm_dma_kernel(GemmDescT<double> d) {
     constexpr int BK = kBK;
     constexpr int FM = BM / 32, FN = BN / 32;
     using LA = Lay<BM, TA>;
@@ -753,15 +753,13 @@ __global__ __launch_bounds__(256, 2) void dgemm_dma_kernel(GemmDescT<double> d) 
     // Three LDS stages of A and B slices; after the k-loop the same memory
     // holds the output tile for the coalesced epilogue.
     __shared__ __align__(16) double lds[3 * (NA + NB)];
-    double* const As0 = lds;
-    double* const As1 = lds + NA;
-    double* const As2 = lds + 2 * NA;
-    double* const Bs0 = lds + 3 * NA;
-    double* const Bs1 = lds + 3 * NA + NB;
-    double* const Bs2 = lds + 3 * NA + 2 * NB;
+    // Stage s: A slice at lds + s NA, B slice at lds + 3 NA + s NB.
     // Output tile in LDS, column-major with a padded leading dimension.
+    // A tile too large for them goes out in two passes of BN / 2 columns.
     constexpr int TLD = BM + 2;
-    static_assert(BN * TLD <= 3 * (NA + NB), "the output tile fits in the stage buffers");
+    constexpr int EC = BN * TLD <= 3 * (NA + NB) ? BN : BN / 2;   // columns per epilogue pass
+    static_assert(EC * TLD <= 3 * (NA + NB), "an epilogue pass fits in the stage buffers");
+    static_assert(!PRE || EC == BN, "Cin loaded before the k-loop needs a one-pass epilogue");
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wv = __builtin_amdgcn_readfirstlane(wave);
@@ -811,117 +809,120 @@ __global__ __launch_bounds__(256, 2) void dgemm_dma_kernel(GemmDescT<double> d) 
     const double* Cin = d.Cin ? d.Cin + (long long)ob * d.strideCin + (long long)z2 * d.strideCin2 : nullptr;
     const double alpha = d.alpha, beta = d.beta;
     const bool use_cin = !split && Cin != nullptr && d.beta != 0.0;
-    // Cin in the coalesced layout of the epilogue: wave w takes the tile's
-    // columns w, w + 4, ..., lane l its rows l, l + 64, ...; each load
-    // instruction reads one column segment of 64 rows.
-    constexpr int CPW = BN / 4, RPL = BM / 64;
+    // Cin in the coalesced layout of the epilogue: in a pass over columns
+    // cb .. cb + EC - 1, wave w takes columns cb + w, cb + w + 4, ..., lane l
+    // its rows l, l + 64, ...; each load instruction reads one column
+    // segment of 64 rows.
+    constexpr int CPW = EC / 4, RPL = BM / 64;
     double cin[CPW][RPL];
-    auto load_cin = [&]() __attribute__((always_inline)) {
+    auto load_cin = [&](int cb) __attribute__((always_inline)) {
 #pragma unroll
         for (int q = 0; q < CPW; ++q)
 #pragma unroll
             for (int u = 0; u < RPL; ++u) {
                 const int gi = row0 + lane + 64 * u;
-                const int gj = col0 + wv + 4 * q;
+                const int gj = col0 + cb + wv + 4 * q;
                 const bool ok = gi < d.m && gj < d.n;
                 cin[q][u] = Cin[ok ? gi + (long long)gj * d.ldcin : 0];
             }
     };
-    if (PRE && use_cin) load_cin();
+    if (PRE && use_cin) load_cin(0);
 
-    // Rows of op(A) past m and columns of op(B) past n only reach outputs
-    // that are never stored, so the copies of an edge tile read clamped rows
-    // (columns) instead of masking them.  A pair of rows (R-layout) must not
-    // straddle the edge: with an odd extent such tiles take the masked path.
-    const bool a_edge_ok = row0 + BM <= d.m || TA || (d.m & 1) == 0;
-    const bool b_edge_ok = col0 + BN <= d.n || !TB || (d.n & 1) == 0;
+    // Each lane loads 16-byte chunks (two elements adjacent in memory) of
+    // the slice into registers and later stores them to its slots of the
+    // LDS layout.  The dispatcher only sends launches whose chunks are all
+    // 16-byte aligned and never straddle an edge (even extents along pairs,
+    // even leading dimensions and strides, even k for operands contiguous
+    // along k), so every slice issues the same loads from in-bounds
+    // addresses: rows of op(A) past m (columns of op(B) past n) are clamped
+    // to the last pair (they only reach outputs that are never stored), k
+    // past the slice's range is clamped to its last pair, and elements
+    // outside the k-range or the triangle of a triangular operand are set
+    // to zero in registers before the store.
+    constexpr int KA = LA::kPerWave, KB = LB::kPerWave;
     const int a_last = TA ? d.m - 1 : d.m - 2, b_last = TB ? d.n - 2 : d.n - 1;
-    const bool lda_even = (d.lda & 1) == 0, ldb_even = (d.ldb & 1) == 0;
-
-    // Per-lane element offsets of this wave's DMA chunks, less the k0 term.
-    long long dA[LA::kPerWave], dB[LB::kPerWave];
+    const long long ka = TA ? 1 : d.lda, kbs = TB ? d.ldb : 1;   // offset step per k
+    // Per chunk: element offset of its (clamped) row or column and its k
+    // within the slice, relative to the slice's first k.
+    long long dA[KA], dB[KB];
 #pragma unroll
-    for (int q = 0; q < LA::kPerWave; ++q) {
+    for (int q = 0; q < KA; ++q) {
         int r, kk;
-        LA::coords((wv * LA::kPerWave + q) * 64 + lane, r, kk);
+        LA::coords((wv * KA + q) * 64 + lane, r, kk);
         const int gi = max(min(row0 + r, a_last), 0);
         dA[q] = TA ? kk + (long long)gi * d.lda : gi + (long long)kk * d.lda;
     }
 #pragma unroll
-    for (int q = 0; q < LB::kPerWave; ++q) {
+    for (int q = 0; q < KB; ++q) {
         int r, kk;
-        LB::coords((wv * LB::kPerWave + q) * 64 + lane, r, kk);
+        LB::coords((wv * KB + q) * 64 + lane, r, kk);
         const int gj = max(min(col0 + r, b_last), 0);
         dB[q] = TB ? gj + (long long)kk * d.ldb : kk + (long long)gj * d.ldb;
     }
-    const long long ka = TA ? 1 : d.lda, kbs = TB ? d.ldb : 1;   // offset step per k
+    // Slices with k0 >= kfull_lo and k0 + BK <= kfull_hi need no zeroing:
+    // inside the k-range and clear of the diagonal of a triangular operand.
+    int kfull_lo = kb, kfull_hi = ke;
+    if (fl & kAUpper) kfull_lo = max(kfull_lo, row0 + BM - 1);
+    if (fl & kBLower) kfull_lo = max(kfull_lo, col0 + BN - 1);
+    if (fl & kALower) kfull_hi = min(kfull_hi, row0 + 1);
+    if (fl & kBUpper) kfull_hi = min(kfull_hi, col0 + 1);
 
-    // Stage slice t of the (batch, k) sequence into one LDS stage.  Returns
-    // the number of DMA instructions this wave left in flight.
-    auto issue = [&](int t, double* sa, double* sb) __attribute__((always_inline)) -> int {
+    // Load slice t of the (batch, k) sequence into registers.  A ragged
+    // last slice loads the last BK values of k instead (ke >= BK here), the
+    // part it shares with the slice before being zeroed at the store, so
+    // every load stays in bounds with no per-chunk clamp.  Slices past the
+    // range reload the last one (never stored): every trip of the loop
+    // issues the same loads, and the compiler's wait counts let the newer
+    // register set stay in flight while the older one is stored.
+    auto gload = [&](int t, dpair (&ra)[KA], dpair (&rb)[KB]) __attribute__((always_inline)) {
+        t = min(t, t_end - 1);
         const int bi = t / nk;
-        const int k0 = kb + (t - bi * nk) * BK;
+        const int k0 = min(kb + (t - bi * nk) * BK, ke - BK);
         const int b = bfirst + bi;
-        const double* __restrict__ A = d.A + (long long)b * d.strideA + (long long)z2 * d.strideA2;
-        const double* __restrict__ B = d.B + (long long)b * d.strideB + (long long)z2 * d.strideB2;
-        bool fast = a_edge_ok && b_edge_ok && k0 + BK <= ke && lda_even && ldb_even &&
-                    ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 15) == 0;
-        if (fl & kAUpper) fast = fast && k0 >= row0 + BM - 1;
-        if (fl & kALower) fast = fast && k0 + BK - 1 <= row0;
-        if (fl & kBUpper) fast = fast && k0 + BK - 1 <= col0;
-        if (fl & kBLower) fast = fast && k0 >= col0 + BN - 1;
-        if (fast) {
-            const double* Ak = A + (long long)k0 * ka;
-            const double* Bk = B + (long long)k0 * kbs;
-            const unsigned la = __builtin_amdgcn_readfirstlane(lds_addr(sa) + wv * LA::kPerWave * 1024);
-            const unsigned lb = __builtin_amdgcn_readfirstlane(lds_addr(sb) + wv * LB::kPerWave * 1024);
+        const double* __restrict__ Ak = d.A + (long long)b * d.strideA + (long long)z2 * d.strideA2 + (long long)k0 * ka;
+        const double* __restrict__ Bk = d.B + (long long)b * d.strideB + (long long)z2 * d.strideB2 + (long long)k0 * kbs;
 #pragma unroll
-            for (int q = 0; q < LA::kPerWave; ++q) copy_to_lds16(Ak + dA[q], la + q * 1024);
+        for (int q = 0; q < KA; ++q) ra[q] = *reinterpret_cast<const dpair*>(Ak + dA[q]);
 #pragma unroll
-            for (int q = 0; q < LB::kPerWave; ++q) copy_to_lds16(Bk + dB[q], lb + q * 1024);
-            return LA::kPerWave + LB::kPerWave;
+        for (int q = 0; q < KB; ++q) rb[q] = *reinterpret_cast<const dpair*>(Bk + dB[q]);
+    };
+    // Zero the elements of slice t that lie outside [kq, ke) (kq: the
+    // slice's first k; below it only for a shifted ragged slice) or outside
+    // the triangle of a triangular operand (rare: the ragged last slice and
+    // the diagonal blocks), then store the slice to an LDS stage.
+    auto sstore = [&](int t, dpair (&ra)[KA], dpair (&rb)[KB], double* sa, double* sb) __attribute__((always_inline)) {
+        const int kq = kb + (t % nk) * BK;
+        const int k0 = min(kq, ke - BK);
+        if (kq < kfull_lo || kq + BK > kfull_hi) {
+#pragma unroll
+            for (int q = 0; q < KA; ++q)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    int r, kk;
+                    LA::coords((wv * KA + q) * 64 + lane, r, kk);
+                    const int gi = row0 + r + (TA ? 0 : h), gk = k0 + kk + (TA ? h : 0);
+                    bool ok = gk >= kq && gk < ke;
+                    if (fl & kAUpper) ok = ok && gk >= gi;
+                    if (fl & kALower) ok = ok && gk <= gi;
+                    ra[q][h] = ok ? ra[q][h] : 0.0;
+                }
+#pragma unroll
+            for (int q = 0; q < KB; ++q)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    int r, kk;
+                    LB::coords((wv * KB + q) * 64 + lane, r, kk);
+                    const int gj = col0 + r + (TB ? h : 0), gk = k0 + kk + (TB ? 0 : h);
+                    bool ok = gk >= kq && gk < ke;
+                    if (fl & kBUpper) ok = ok && gk <= gj;
+                    if (fl & kBLower) ok = ok && gk >= gj;
+                    rb[q][h] = ok ? rb[q][h] : 0.0;
+                }
         }
-        // Masked staging through registers, same chunk layout (rare: its
-        // lane-dependent terms are recomputed here rather than kept live).
-        int ln = lane;
-        asm volatile("" : "+v"(ln));
 #pragma unroll
-        for (int q = 0; q < LA::kPerWave; ++q) {
-            const int ins = wv * LA::kPerWave + q, slot = ins * 64 + ln;
-            int r, kk;
-            LA::coords(slot, r, kk);
-            double v[2];
+        for (int q = 0; q < KA; ++q) *reinterpret_cast<dpair*>(sa + 2 * ((wv * KA + q) * 64 + lane)) = ra[q];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int gi = row0 + r + (TA ? 0 : h), gk = k0 + kk + (TA ? h : 0);
-                bool ok = gi < d.m && gk < ke;
-                if (fl & kAUpper) ok = ok && gk >= gi;
-                if (fl & kALower) ok = ok && gk <= gi;
-                const long long off = TA ? gk + (long long)gi * d.lda : gi + (long long)gk * d.lda;
-                const double x = A[ok ? off : 0];
-                v[h] = ok ? x : 0.0;
-            }
-            *reinterpret_cast<dpair*>(sa + 2 * slot) = dpair{v[0], v[1]};
-        }
-#pragma unroll
-        for (int q = 0; q < LB::kPerWave; ++q) {
-            const int ins = wv * LB::kPerWave + q, slot = ins * 64 + ln;
-            int r, kk;
-            LB::coords(slot, r, kk);
-            double v[2];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int gj = col0 + r + (TB ? h : 0), gk = k0 + kk + (TB ? 0 : h);
-                bool ok = gj < d.n && gk < ke;
-                if (fl & kBUpper) ok = ok && gk <= gj;
-                if (fl & kBLower) ok = ok && gk >= gj;
-                const long long off = TB ? gj + (long long)gk * d.ldb : gk + (long long)gj * d.ldb;
-                const double x = B[ok ? off : 0];
-                v[h] = ok ? x : 0.0;
-            }
-            *reinterpret_cast<dpair*>(sb + 2 * slot) = dpair{v[0], v[1]};
-        }
-        return 0;
+        for (int q = 0; q < KB; ++q) *reinterpret_cast<dpair*>(sb + 2 * ((wv * KB + q) * 64 + lane)) = rb[q];
     };
 
     // Per-lane byte offsets of the MFMA fragments at the first 4-deep step;
@@ -951,6 +952,10 @@ __global__ __launch_bounds__(256, 2) void dgemm_dma_kernel(GemmDescT<double> d) 
                 for (int j = 0; j < FN; ++j)
                     bf[p ^ 1][j] = *reinterpret_cast<const double*>(cb + LB::offset(wn + j * 16 + ra0, 4 * (s4 + 1) + kl));
             }
+            // Keep the next step's fragment reads ahead of this step's MFMAs
+            // (the scheduler otherwise sinks them below the MFMAs into the
+            // registers those MFMAs read, and each step waits on its reads).
+            __builtin_amdgcn_sched_barrier(0);
             if (SCALE) {
 #pragma unroll
                 for (int i = 0; i < FM; ++i) af[p][i] *= al;
@@ -961,50 +966,55 @@ __global__ __launch_bounds__(256, 2) void dgemm_dma_kernel(GemmDescT<double> d) 
                 for (int j = 0; j < FN; ++j) acc[i][j] = mfma_f64_16x16x4(af[p][i], bf[p][j], acc[i][j]);
         }
     };
-    const bool scaled = d.nalpha > 0;
-    auto compute = [&](const double* sa, const double* sb, int t) __attribute__((always_inline)) {
-        if (scaled) compute_k(sa, sb, t, std::true_type{});
-        else compute_k(sa, sb, t, std::false_type{});
-    };
 
-    // Three-stage ring, loads two slices ahead.  Before the barrier that
-    // opens slice u each wave waits for its own loads of slice u (those of
-    // slice u+1 may stay in flight); the barrier also ends every read of
-    // the stage that slice u+2 then refills.
-    // The barrier is written out: __syncthreads() would also wait for every
-    // load in flight, including the next slice's.  LDS writes of a masked
-    // slice are waited for (lgkmcnt) before it.
-    auto wait_for = [&](int inflight_next) __attribute__((always_inline)) {
-        if (inflight_next >= 6) __builtin_amdgcn_s_waitcnt(0x0F76);
-        else if (inflight_next == 4) __builtin_amdgcn_s_waitcnt(0x0F74);
-        else __builtin_amdgcn_s_waitcnt(0x0F70);
-    };
+    // Two LDS stages and two register sets.  While slice u is multiplied
+    // from LDS, slice u + 1 waits in registers and slice u + 2 is loaded
+    // into the other set; slice u + 1 then goes to the stage slice u - 1
+    // left (every wave finished reading it before the previous barrier).
+    // The barrier waits for the LDS stores only: the loads in flight belong
+    // to this wave's registers.  The loop body covers two slices so that
+    // both register sets are named statically; it is instantiated once with
+    // and once without the per-batch scale, since a run-time choice inside
+    // it made the compiler keep a second set of accumulators and copy
+    // between the two sets.
     auto barrier = [&]() __attribute__((always_inline)) {
         __builtin_amdgcn_s_waitcnt(0xC07F);
         asm volatile("" ::: "memory");
         __builtin_amdgcn_s_barrier();
         asm volatile("" ::: "memory");
     };
-    if (nt > 0) {
-        int n0 = issue(t_begin, As0, Bs0);
-        int n1 = nt > 1 ? issue(t_begin + 1, As1, Bs1) : 0;
-        (void)n0;
-        for (int u = 0; u < nt; u += 3) {
-            wait_for(u + 1 < nt ? n1 : 0);
+    double* const sA0 = lds;
+    double* const sA1 = lds + NA;
+    double* const sB0 = lds + 3 * NA;
+    double* const sB1 = lds + 3 * NA + NB;
+    auto kloop = [&](auto scale_) __attribute__((always_inline)) {
+        if (nt <= 0) return;
+        dpair ra0[KA], rb0[KB], ra1[KA], rb1[KB];
+        gload(t_begin, ra0, rb0);
+        sstore(t_begin, ra0, rb0, sA0, sB0);
+        gload(t_begin + 1, ra1, rb1);
+        barrier();
+        int u = 0;
+        for (; u + 1 < nt; u += 2) {
+            gload(t_begin + u + 2, ra0, rb0);
+            compute_k(sA0, sB0, t_begin + u, scale_);
+            sstore(t_begin + u + 1, ra1, rb1, sA1, sB1);
             barrier();
-            int n2 = u + 2 < nt ? issue(t_begin + u + 2, As2, Bs2) : 0;
-            compute(As0, Bs0, t_begin + u);
-            if (u + 1 >= nt) break;
-            wait_for(u + 2 < nt ? n2 : 0);
+            gload(t_begin + u + 3, ra1, rb1);
+            compute_k(sA1, sB1, t_begin + u + 1, scale_);
+            if (u + 2 < nt) sstore(t_begin + u + 2, ra0, rb0, sA0, sB0);
             barrier();
-            int n3 = u + 3 < nt ? issue(t_begin + u + 3, As0, Bs0) : 0;
-            compute(As1, Bs1, t_begin + u + 1);
-            if (u + 2 >= nt) break;
-            wait_for(u + 3 < nt ? n3 : 0);
-            barrier();
-            n1 = u + 4 < nt ? issue(t_begin + u + 4, As1, Bs1) : 0;
-            compute(As2, Bs2, t_begin + u + 2);
         }
+        if (u < nt) compute_k(sA0, sB0, t_begin + u, scale_);
+    };
+    // 128 x 128 tiles take no per-batch scale (the dispatcher sends such
+    // products to the smaller tiles): one loop, one home for the
+    // accumulators.
+    if constexpr (BM * BN >= 128 * 128) {
+        kloop(std::false_type{});
+    } else {
+        if (d.nalpha > 0) kloop(std::true_type{});
+        else kloop(std::false_type{});
     }
 
     // Split-K pieces store their partial sums as they are (m x n, column-major)
@@ -1020,38 +1030,44 @@ __global__ __launch_bounds__(256, 2) void dgemm_dma_kernel(GemmDescT<double> d) 
         alo = 1.0;
         sfl = 0;
     }
-    // All Cin loads are issued before the first store (Cin and C may alias).
-    if (!PRE && use_cin) load_cin();
-    // The accumulators go through LDS (the stage buffers, once every wave has
-    // finished its last slice) so that each store instruction writes one
-    // column segment of 64 rows instead of sixteen 4-row pieces.
-    __syncthreads();
+    // Each element's Cin value is loaded before that element is stored (Cin
+    // and C may alias).  The accumulators go through LDS (the stage buffers,
+    // once every wave has finished its last slice) so that each store
+    // instruction writes one column segment of 64 rows instead of sixteen
+    // 4-row pieces.
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+    for (int cb = 0; cb < BN; cb += EC) {
+        if (!PRE && use_cin) load_cin(cb);
+        __syncthreads();
+        if (wn >= cb && wn < cb + EC) {
 #pragma unroll
-        for (int j = 0; j < FN; ++j)
+            for (int i = 0; i < FM; ++i)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int r = wm + i * 16 + Mfma<double>::row(lane, e);
-                const int c = wn + j * 16 + (lane & 15);
-                lds[c * TLD + r] = acc[i][j][e];
-            }
-    __syncthreads();
+                for (int j = 0; j < FN; ++j)
 #pragma unroll
-    for (int q = 0; q < CPW; ++q)
-#pragma unroll
-        for (int u = 0; u < RPL; ++u) {
-            const int r = lane + 64 * u, c = wv + 4 * q;
-            const int gi = row0 + r, gj = col0 + c;
-            bool ok = gi < d.m && gj < d.n;
-            if (sfl & kCStoreUpper) ok = ok && gi <= gj;
-            if (sfl & kCStoreLower) ok = ok && gi >= gj;
-            if (ok) {
-                double v = alo * lds[c * TLD + r];
-                if (use_cin) v += beta * cin[q][u];
-                Out[gi + (long long)gj * ldo] = v;
-            }
+                    for (int e = 0; e < 4; ++e) {
+                        const int r = wm + i * 16 + Mfma<double>::row(lane, e);
+                        const int c = wn - cb + j * 16 + (lane & 15);
+                        lds[c * TLD + r] = acc[i][j][e];
+                    }
         }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < CPW; ++q)
+#pragma unroll
+            for (int u = 0; u < RPL; ++u) {
+                const int r = lane + 64 * u, c = wv + 4 * q;
+                const int gi = row0 + r, gj = col0 + cb + c;
+                bool ok = gi < d.m && gj < d.n;
+                if (sfl & kCStoreUpper) ok = ok && gi <= gj;
+                if (sfl & kCStoreLower) ok = ok && gi >= gj;
+                if (ok) {
+                    double v = alo * lds[c * TLD + r];
+                    if (use_cin) v += beta * cin[q][u];
+                    Out[gi + (long long)gj * ldo] = v;
+                }
+            }
+    }
 }
 
 template <int BM, int BN>
@@ -1256,9 +1272,14 @@ int pick_tile(const GemmDescT<T>& d) {
             }
             return 0;
         }
-        const bool even_edges = (d.transa || (d.m & 1) == 0) && (!d.transb || (d.n & 1) == 0);
+        // dgemm_dma_kernel loads 16-byte pairs: they must be aligned and
+        // must not straddle an edge of op(A) or op(B) or the end of k.
+        const bool even_edges = (d.transa || (d.m & 1) == 0) && (!d.transb || (d.n & 1) == 0) &&
+                                ((!d.transa && d.transb) || (d.k & 1) == 0);
         const bool even_ld = (d.lda & 1) == 0 && (d.ldb & 1) == 0;
-        if (even_edges && even_ld) return (d.k > 256 && d.m >= 128 && d.n >= 128 && t1 >= 256) ? 5 : 6;
+        const bool aligned = ((reinterpret_cast<uintptr_t>(d.A) | reinterpret_cast<uintptr_t>(d.B)) & 15) == 0 &&
+                             ((d.strideA | d.strideB | d.strideA2 | d.strideB2) & 1) == 0;
+        if (even_edges && even_ld && aligned) return (d.k > 256 && d.m >= 128 && d.n >= 128 && t1 >= 256) ? 5 : 6;
     }
     if (d.k <= 128) return 0;
     if (d.m >= 128 && d.n >= 128 && t1 >= 256) return 1;
