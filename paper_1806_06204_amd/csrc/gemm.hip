@@ -686,15 +686,17 @@ hipError_t launch_valu(const GemmDescT<double>& desc, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// FP64 MFMA GEMM with operands copied from global memory straight into LDS
-// (global_load_lds_dwordx4).  Staging through registers costs the wave one
-// LDS write per element and a wait on its own loads; measured at 8192^3 the
-// MFMA loop alone runs at 75 TFLOP/s and only 49 with the register-staged
-// LDS writes.  Here each lane's 16-byte load lands in LDS at its lane slot
-// without passing through registers, three LDS stages keep the loads two
-// k-slices ahead, and a slice whose elements need masking (ragged edges,
-// the diagonal block of a triangular operand) or whose source is not
-// 16-byte aligned is staged through registers into the same layout.
+// Pipelined FP64 MFMA GEMM.  Each k-slice (BK = 16) of both operands is
+// loaded by 16-byte loads into registers, stored to one of two LDS stages
+// after the previous slice's MFMAs have been issued, and multiplied from
+// there; the loads of the slice after next are in flight meanwhile.  Within
+// a slice the fragment reads of the next 4-deep step are issued ahead of the
+// current step's MFMAs.  Measured at 8192^3 on gfx950: 68 TFLOP/s (the MFMA
+// loop alone, without global loads, 75).  The same kernel with the slices
+// copied global -> LDS directly (global_load_lds_dwordx4, three stages)
+// reached 58: the copies and their waits left the MFMA pipe idle a quarter
+// of the time (MFMA busy 0.75 against 0.93 for the vendor's FP64 GEMM, and
+// 6.7x its wave-cycles waiting on memory or barriers).
 //
 // Layouts of one operand slice (R rows of op(A), or columns of op(B), by
 // BK = 16), in 16-byte chunks of two elements adjacent in memory:
@@ -703,12 +705,12 @@ hipError_t launch_valu(const GemmDescT<double>& desc, hipStream_t s) {
 //   K-layout (memory contiguous along k: A transposed, B as is): chunk
 //     (r, k/2) at r * 8 + ((k/2) ^ (r & 7)).
 // The XOR terms spread the 16 lanes of an MFMA fragment read over the LDS
-// banks (2-way at most); a DMA instruction of 64 lanes fills 64 consecutive
-// chunks, reading whole 128-byte lines in both layouts.
+// banks (2-way at most); the 64 lanes of a load instruction fill 64
+// consecutive chunks, reading whole 128-byte lines in both layouts.
 template <int R, bool KC>
 struct Lay {
     static constexpr int kChunks = R * kBK / 2;
-    static constexpr int kPerWave = kChunks / 64 / 4;   // DMA instructions per wave and slice
+    static constexpr int kPerWave = kChunks / 64 / 4;   // load instructions per wave and slice
     __device__ static void coords(int slot, int& r, int& kk) {
         if constexpr (!KC) {
             kk = slot / (R / 2);
@@ -724,27 +726,10 @@ struct Lay {
     }
 };
 
-// One 16-byte global -> LDS copy per lane: lane l's bytes land at LDS
-// address lds_base + 16 l.  Written out rather than through the builtin so
-// that the compiler, which cannot tell the three LDS stages' copies apart
-// once the masked staging path joins the loop, does not wait for every copy
-// in flight before each LDS read; the kernel waits for exactly the copies
-// of the slice it is about to read (vmcnt) and publishes them with its
-// barrier.  lds_base is wave-uniform.
-__device__ inline void copy_to_lds16(const double* src, unsigned lds_base) {
-    asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
-                 :
-                 : "v"(src), "s"(lds_base)
-                 : "memory", "m0");
-}
-__device__ inline unsigned lds_addr(const void* p) {
-    return (unsigned)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
-}
-
 // PRE: load the Cin tile before the k-loop (short k-ranges, where its
 // latency would not hide behind the loop); otherwise after it.
 template <int BM, int BN, bool TA, bool TB, bool PRE>
-__global__ __launch_bounds__(256, BM * BN >= 128 * 128 ? 1 : 2) void dgemm_dma_kernel(GemmDescT<double> d) {
+__global__ __launch_bounds__(256, 2) void dgemm_pipe_kernel(GemmDescT<double> d) {
     constexpr int BK = kBK;
     constexpr int FM = BM / 32, FN = BN / 32;
     using LA = Lay<BM, TA>;
@@ -867,6 +852,13 @@ __global__ __launch_bounds__(256, BM * BN >= 128 * 128 ? 1 : 2) void dgemm_dma_k
     if (fl & kALower) kfull_hi = min(kfull_hi, row0 + 1);
     if (fl & kBUpper) kfull_hi = min(kfull_hi, col0 + 1);
 
+    // Odd k with an operand contiguous along k: the pairs of the ragged last
+    // slice would straddle the end of k, so that slice is taken after the
+    // loop with element-wise loads (the dispatcher sends such products only
+    // as launches of one matrix, where it is the last of the sequence).
+    const bool peel = (TA || !TB) && (ke & 1) && t_end == ntiles;
+    const int t_main = peel ? t_end - 1 : t_end;   // end of the pipelined slices
+
     // Load slice t of the (batch, k) sequence into registers.  A ragged
     // last slice loads the last BK values of k instead (ke >= BK here), the
     // part it shares with the slice before being zeroed at the store, so
@@ -875,7 +867,7 @@ __global__ __launch_bounds__(256, BM * BN >= 128 * 128 ? 1 : 2) void dgemm_dma_k
     // issues the same loads, and the compiler's wait counts let the newer
     // register set stay in flight while the older one is stored.
     auto gload = [&](int t, dpair (&ra)[KA], dpair (&rb)[KB]) __attribute__((always_inline)) {
-        t = min(t, t_end - 1);
+        t = min(t, t_main - 1);
         const int bi = t / nk;
         const int k0 = min(kb + (t - bi * nk) * BK, ke - BK);
         const int b = bfirst + bi;
@@ -987,7 +979,7 @@ __global__ __launch_bounds__(256, BM * BN >= 128 * 128 ? 1 : 2) void dgemm_dma_k
     double* const sA1 = lds + NA;
     double* const sB0 = lds + 3 * NA;
     double* const sB1 = lds + 3 * NA + NB;
-    auto kloop = [&](auto scale_) __attribute__((always_inline)) {
+    auto kloop_main = [&](auto scale_, int nt) __attribute__((always_inline)) {
         if (nt <= 0) return;
         dpair ra0[KA], rb0[KB], ra1[KA], rb1[KB];
         gload(t_begin, ra0, rb0);
@@ -1007,15 +999,60 @@ __global__ __launch_bounds__(256, BM * BN >= 128 * 128 ? 1 : 2) void dgemm_dma_k
         }
         if (u < nt) compute_k(sA0, sB0, t_begin + u, scale_);
     };
-    // 128 x 128 tiles take no per-batch scale (the dispatcher sends such
-    // products to the smaller tiles): one loop, one home for the
-    // accumulators.
-    if constexpr (BM * BN >= 128 * 128) {
-        kloop(std::false_type{});
-    } else {
-        if (d.nalpha > 0) kloop(std::true_type{});
-        else kloop(std::false_type{});
-    }
+    // The peeled slice: element-wise loads, zero outside [k0, ke) and the
+    // triangle of a triangular operand, stored straight to LDS stage 0.
+    auto peel_store = [&](int t) __attribute__((always_inline)) {
+        const int bi = t / nk;
+        const int k0 = kb + (t - bi * nk) * BK;
+        const int b = bfirst + bi;
+        const double* __restrict__ A = d.A + (long long)b * d.strideA + (long long)z2 * d.strideA2;
+        const double* __restrict__ B = d.B + (long long)b * d.strideB + (long long)z2 * d.strideB2;
+#pragma unroll 1
+        for (int q = 0; q < KA; ++q) {
+            int r, kk;
+            LA::coords((wv * KA + q) * 64 + lane, r, kk);
+            double v[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int gi = row0 + r + (TA ? 0 : h), gk = k0 + kk + (TA ? h : 0);
+                bool ok = gi < d.m && gk < ke;
+                if (fl & kAUpper) ok = ok && gk >= gi;
+                if (fl & kALower) ok = ok && gk <= gi;
+                const long long off = TA ? gk + (long long)gi * d.lda : gi + (long long)gk * d.lda;
+                const double x = A[ok ? off : 0];
+                v[h] = ok ? x : 0.0;
+            }
+            *reinterpret_cast<dpair*>(sA0 + 2 * ((wv * KA + q) * 64 + lane)) = dpair{v[0], v[1]};
+        }
+#pragma unroll 1
+        for (int q = 0; q < KB; ++q) {
+            int r, kk;
+            LB::coords((wv * KB + q) * 64 + lane, r, kk);
+            double v[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int gj = col0 + r + (TB ? h : 0), gk = k0 + kk + (TB ? 0 : h);
+                bool ok = gj < d.n && gk < ke;
+                if (fl & kBUpper) ok = ok && gk <= gj;
+                if (fl & kBLower) ok = ok && gk >= gj;
+                const long long off = TB ? gj + (long long)gk * d.ldb : gk + (long long)gj * d.ldb;
+                const double x = B[ok ? off : 0];
+                v[h] = ok ? x : 0.0;
+            }
+            *reinterpret_cast<dpair*>(sB0 + 2 * ((wv * KB + q) * 64 + lane)) = dpair{v[0], v[1]};
+        }
+    };
+    auto kloop = [&](auto scale_) __attribute__((always_inline)) {
+        kloop_main(scale_, t_main - t_begin);
+        if (peel) {
+            barrier();   // every wave is past its reads of stage 0
+            peel_store(t_main);
+            barrier();
+            compute_k(sA0, sB0, t_main, scale_);
+        }
+    };
+    if (d.nalpha > 0) kloop(std::true_type{});
+    else kloop(std::false_type{});
 
     // Split-K pieces store their partial sums as they are (m x n, column-major)
     // through the same coalesced epilogue.
@@ -1071,13 +1108,13 @@ __global__ __launch_bounds__(256, BM * BN >= 128 * 128 ? 1 : 2) void dgemm_dma_k
 }
 
 template <int BM, int BN>
-hipError_t launch_dma(const GemmDescT<double>& desc, hipStream_t s) {
+hipError_t launch_pipe(const GemmDescT<double>& desc, hipStream_t s) {
     GemmDescT<double> d = desc;
     const int gx = balance_xcds<double, BM, BN>(d, (d.m + BM - 1) / BM, (d.n + BN - 1) / BN);
     dim3 grid(gx, d.reduce ? 1 : d.batch, d.splitk > 1 ? d.splitk : d.batch2);
     char name[64];
     if (stats_on()) {
-        snprintf(name, sizeof(name), "dgemm_dma<%d,%d,%c,%c>", BM, BN, d.transa ? 'T' : 'N', d.transb ? 'T' : 'N');
+        snprintf(name, sizeof(name), "dgemm_pipe<%d,%d,%c,%c>", BM, BN, d.transa ? 'T' : 'N', d.transb ? 'T' : 'N');
     } else {
         name[0] = 0;
     }
@@ -1085,16 +1122,16 @@ hipError_t launch_dma(const GemmDescT<double>& desc, hipStream_t s) {
     const bool pre = d.k <= 256 && BM * BN <= 64 * 64;
     const int which = (d.transa ? 2 : 0) + (d.transb ? 1 : 0) + (pre ? 4 : 0);
     switch (which) {
-        case 0: dgemm_dma_kernel<BM, BN, false, false, false><<<grid, 256, 0, s>>>(d); break;
-        case 1: dgemm_dma_kernel<BM, BN, false, true, false><<<grid, 256, 0, s>>>(d); break;
-        case 2: dgemm_dma_kernel<BM, BN, true, false, false><<<grid, 256, 0, s>>>(d); break;
-        case 3: dgemm_dma_kernel<BM, BN, true, true, false><<<grid, 256, 0, s>>>(d); break;
+        case 0: dgemm_pipe_kernel<BM, BN, false, false, false><<<grid, 256, 0, s>>>(d); break;
+        case 1: dgemm_pipe_kernel<BM, BN, false, true, false><<<grid, 256, 0, s>>>(d); break;
+        case 2: dgemm_pipe_kernel<BM, BN, true, false, false><<<grid, 256, 0, s>>>(d); break;
+        case 3: dgemm_pipe_kernel<BM, BN, true, true, false><<<grid, 256, 0, s>>>(d); break;
         default:
             if constexpr (BM * BN <= 64 * 64) {
-                if (which == 4) dgemm_dma_kernel<BM, BN, false, false, true><<<grid, 256, 0, s>>>(d);
-                else if (which == 5) dgemm_dma_kernel<BM, BN, false, true, true><<<grid, 256, 0, s>>>(d);
-                else if (which == 6) dgemm_dma_kernel<BM, BN, true, false, true><<<grid, 256, 0, s>>>(d);
-                else dgemm_dma_kernel<BM, BN, true, true, true><<<grid, 256, 0, s>>>(d);
+                if (which == 4) dgemm_pipe_kernel<BM, BN, false, false, true><<<grid, 256, 0, s>>>(d);
+                else if (which == 5) dgemm_pipe_kernel<BM, BN, false, true, true><<<grid, 256, 0, s>>>(d);
+                else if (which == 6) dgemm_pipe_kernel<BM, BN, true, false, true><<<grid, 256, 0, s>>>(d);
+                else dgemm_pipe_kernel<BM, BN, true, true, true><<<grid, 256, 0, s>>>(d);
             }
             break;
     }
@@ -1108,7 +1145,7 @@ hipError_t launch_dma(const GemmDescT<double>& desc, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Run-time tile choice for the DMA kernel (FP64 MFMA).  Its tile shapes
+// Run-time tile choice for the pipelined FP64 MFMA kernel.  Its tile shapes
 // give bit-identical results (each output sums the same products in the same
 // k order; masked terms are exact zeros), so the first calls of a shape
 // class rotate through the candidates on real work, time each with events
@@ -1117,7 +1154,7 @@ hipError_t launch_dma(const GemmDescT<double>& desc, hipStream_t s) {
 // (their piece boundaries depend on the tile).  Off unless ZOLO_AUTOTUNE=1
 // or zolo_autotune_enable(1): the fixed rule is as fast on the Zolo-PD
 // workloads, and keeps which kernel runs independent of timing noise.
-constexpr int kTuneCand = 3;  // DMA 64 x 128, 64 x 64, 128 x 64
+constexpr int kTuneCand = 3;  // 64 x 128, 64 x 64, 128 x 64
 struct TuneKey {
     int dev, ta, tb, reduce, lm, ln, lk;
     unsigned flags;
@@ -1175,21 +1212,21 @@ int ilog2(long long x) {
     return l;
 }
 
-hipError_t launch_dma_cand(int c, const GemmDescT<double>& d, hipStream_t s) {
-    if (c == 0) return launch_dma<64, 128>(d, s);
-    if (c == 1) return launch_dma<64, 64>(d, s);
-    return launch_dma<128, 64>(d, s);
+hipError_t launch_pipe_cand(int c, const GemmDescT<double>& d, hipStream_t s) {
+    if (c == 0) return launch_pipe<64, 128>(d, s);
+    if (c == 1) return launch_pipe<64, 64>(d, s);
+    return launch_pipe<128, 64>(d, s);
 }
 
-hipError_t dispatch_dma_tuned(const GemmDescT<double>& d, int static_choice, hipStream_t s) {
-    if (!autotune_on() || d.splitk > 1) return launch_dma_cand(static_choice, d, s);
+hipError_t dispatch_pipe_tuned(const GemmDescT<double>& d, int static_choice, hipStream_t s) {
+    if (!autotune_on() || d.splitk > 1) return launch_pipe_cand(static_choice, d, s);
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return launch_dma_cand(static_choice, d, s);
+    if (hipGetDevice(&dev) != hipSuccess) return launch_pipe_cand(static_choice, d, s);
     const TuneKey key{dev, d.transa, d.transb, d.reduce ? 1 : 0, ilog2(d.m), ilog2(d.n), ilog2(d.k), d.flags,
                       d.Cin != nullptr && d.beta != 0.0};
     std::lock_guard<std::mutex> lock(g_tune_mu);
     TuneEntry& e = g_tune[key];
-    if (e.chosen >= 0) return launch_dma_cand(e.chosen, d, s);
+    if (e.chosen >= 0) return launch_pipe_cand(e.chosen, d, s);
     int done = 0;
     for (int q = 0; q < e.launched; ++q) {
         if (!e.measured[q] && hipEventQuery(e.ev[q][1]) == hipSuccess &&
@@ -1222,29 +1259,30 @@ hipError_t dispatch_dma_tuned(const GemmDescT<double>& d, int static_choice, hip
         }
         for (int q = 0; q < kTuneSlots; ++q)
             for (int h = 0; h < 2; ++h) (void)hipEventDestroy(e.ev[q][h]);
-        return launch_dma_cand(best, d, s);
+        return launch_pipe_cand(best, d, s);
     }
     if (e.launched < kTuneSlots) {
         const int q = e.launched, c = kTuneOrder[q];
-        if (hipEventCreate(&e.ev[q][0]) != hipSuccess) return launch_dma_cand(static_choice, d, s);
+        if (hipEventCreate(&e.ev[q][0]) != hipSuccess) return launch_pipe_cand(static_choice, d, s);
         if (hipEventCreate(&e.ev[q][1]) != hipSuccess) {
             (void)hipEventDestroy(e.ev[q][0]);
-            return launch_dma_cand(static_choice, d, s);
+            return launch_pipe_cand(static_choice, d, s);
         }
         ++e.launched;
         e.flops[q] = gemm_flops(d);
         hipError_t err = hipEventRecord(e.ev[q][0], s);
-        if (err == hipSuccess) err = launch_dma_cand(c, d, s);
+        if (err == hipSuccess) err = launch_pipe_cand(c, d, s);
         if (err == hipSuccess) err = hipEventRecord(e.ev[q][1], s);
         return err;
     }
-    return launch_dma_cand(static_choice, d, s);
+    return launch_pipe_cand(static_choice, d, s);
 }
 
 // Kernel and tile shape for a descriptor: 0/1 = MFMA gemm_kernel with
 // 64 x 64 / 64 x 128 tiles, 4 = dgemm_valu_kernel (128 x 128),
-// 5/6 = dgemm_dma_kernel with 64 x 128 / 64 x 64 tiles.  Measured on gfx950
-// (FP64, TFLOP/s; gemm_kernel / vector / DMA kernel):
+// 5/6 = dgemm_pipe_kernel with 64 x 128 / 64 x 64 tiles.  Measured on gfx950
+// (FP64, TFLOP/s; gemm_kernel / vector / the pipelined kernel's earlier form
+// with direct global -> LDS copies):
 //   8192^3 N,N                          39.7 / 46.0 / 56.9
 //   8192^3 T,N upper tiles (Gram)       37.3 / 35.3 / 52.9
 //   8192^3 x 8 N,T batch-reduced        38.5 / 43.3 / 51.2
@@ -1253,13 +1291,14 @@ hipError_t dispatch_dma_tuned(const GemmDescT<double>& d, int static_choice, hip
 //   8320 x 8064 x 128 x 8 N,N (k=128)   14.2 / 16.0 / 15.9
 //   7936^2 x 64 x 8 T,N upper (k=64)    18.6 / 20.8 / 18.9
 //   8320 x 7936 x 256 x 8 N,N (k=256)   30.5 / 36.2 / 37.9 (64 x 64 tiles: 40.5)
-// (counting the nonzeros of trapezoidal operands).  Up to k = 256 the DMA
-// kernel runs 64 x 64 tiles, three workgroups per CU, with Cin loaded before
-// the k-loop; beyond, 64 x 128 and 64 x 64 tiles are equally fast at 8192^3.
-// 64-row MFMA tiles run two workgroups per CU and beat 128 x 128 MFMA tiles
-// on every shape (35 against 40 at 8192^3).  The DMA kernel stages edge
-// tiles through registers when an extent along which its copies run is odd,
-// which is slower than gemm_kernel on small ragged products.
+// (counting the nonzeros of trapezoidal operands).  The pipelined kernel as
+// it stands: 8192^3 N,N 68.3, T,N 68.5, N,T 63.5; 256 x 8192 x 8256 x 8 T,N
+// 65.1; 8256 x 8192 x 256 x 8 N,N with C read 50.1.  Up to k = 256 it runs
+// 64 x 64 tiles, three workgroups per CU, with Cin loaded before the k-loop;
+// beyond, 64 x 128 tiles.  128 x 128 tiles (one workgroup per CU) were
+// slower in both the earlier and the current form.  64-row MFMA tiles of
+// gemm_kernel run two workgroups per CU and beat its 128 x 128 tiles on
+// every shape (35 against 40 at 8192^3).
 template <class T>
 int pick_tile(const GemmDescT<T>& d) {
     const long long nb = (long long)(d.reduce ? 1 : d.batch) * d.batch2;
@@ -1272,10 +1311,13 @@ int pick_tile(const GemmDescT<T>& d) {
             }
             return 0;
         }
-        // dgemm_dma_kernel loads 16-byte pairs: they must be aligned and
-        // must not straddle an edge of op(A) or op(B) or the end of k.
+        // dgemm_pipe_kernel loads 16-byte pairs: they must be aligned and
+        // must not straddle an edge of op(A) or op(B); with odd k and an
+        // operand contiguous along k it takes the ragged last slice apart,
+        // which only works when that slice ends the sequence (no sum over
+        // the batch).
         const bool even_edges = (d.transa || (d.m & 1) == 0) && (!d.transb || (d.n & 1) == 0) &&
-                                ((!d.transa && d.transb) || (d.k & 1) == 0);
+                                ((!d.transa && d.transb) || (d.k & 1) == 0 || !(d.reduce && d.batch > 1));
         const bool even_ld = (d.lda & 1) == 0 && (d.ldb & 1) == 0;
         const bool aligned = ((reinterpret_cast<uintptr_t>(d.A) | reinterpret_cast<uintptr_t>(d.B)) & 15) == 0 &&
                              ((d.strideA | d.strideB | d.strideA2 | d.strideB2) & 1) == 0;
@@ -1300,8 +1342,8 @@ hipError_t gemm_dispatch(const GemmDescT<T>& d, hipStream_t s) {
     const int t = pick_tile(d);
     if constexpr (sizeof(T) == 8) {
         if (t == 4) return launch_valu(d, s);
-        if (t == 5) return dispatch_dma_tuned(d, 0, s);
-        if (t == 6) return dispatch_dma_tuned(d, 1, s);
+        if (t == 5) return dispatch_pipe_tuned(d, 0, s);
+        if (t == 6) return dispatch_pipe_tuned(d, 1, s);
     }
     switch (t) {
         case 0: return launch_bm_bn<T, 64, 64>(d, s);

@@ -76,10 +76,12 @@ def test_gemm_vector_kernel_shapes(z, ta, tb):
 
 @pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
 @pytest.mark.parametrize("m,n,k", [(130, 258, 300), (131, 257, 517), (256, 384, 1000), (64, 64, 129)])
-def test_gemm_lds_copy_kernel_shapes(z, ta, tb, m, n, k):
-    # Long-k products (the LDS-copy kernel where its rule takes them): even
-    # and odd edges (clamped copies / masked staging), k not a multiple of
-    # the 16-deep slice, batch 3, alpha and beta.
+def test_gemm_pipe_kernel_shapes(z, ta, tb, m, n, k):
+    # Long-k products (the pipelined kernel where its rule takes them): even
+    # and odd edges (clamped rows), k not a multiple of the 16-deep slice
+    # (even: the last slice shifted back and its overlap zeroed; odd with an
+    # operand contiguous along k: the last slice taken apart with
+    # element-wise loads), batch 3, alpha and beta.
     rng = np.random.default_rng(m + 3 * n + 7 * k + 2 * ta + tb)
     batch = 3
     A = rng.standard_normal((batch, k, m) if ta else (batch, m, k))
@@ -95,7 +97,7 @@ def test_gemm_lds_copy_kernel_shapes(z, ta, tb, m, n, k):
 @pytest.mark.parametrize("ta,tb,m,n,k", [(0, 0, 130, 258, 300), (1, 0, 131, 257, 518), (0, 1, 256, 384, 1000),
                                           (1, 1, 192, 320, 160)])
 def test_gemm_autotune_bitwise(z, ta, tb, m, n, k):
-    # The autotuner runs every candidate tile shape of the LDS-copy kernel on
+    # The autotuner runs every candidate tile shape of the pipelined kernel on
     # the first calls of a shape class, then the fastest: every call must
     # give the same bits, and all three shapes must have run.
     from paper_1806_06204_amd import zolo
@@ -110,12 +112,12 @@ def test_gemm_autotune_bitwise(z, ta, tb, m, n, k):
     zolo.stats_reset()
     try:
         outs = [z.gemm(dA, dB, dC, transa=ta, transb=tb, alpha=0.7, beta=1.5).cpu().numpy() for _ in range(8)]
-        names = {nm for nm in zolo.stats() if nm.startswith("dgemm_dma<")}
+        names = {nm for nm in zolo.stats() if nm.startswith("dgemm_pipe<")}
     finally:
         zolo.stats_enable(False)
         zolo.autotune_enable(False)
     tag = ",%s,%s>" % ("T" if ta else "N", "T" if tb else "N")
-    assert names == {"dgemm_dma<%d,%d%s" % (bm, bn, tag) for bm, bn in ((64, 128), (64, 64), (128, 64))}
+    assert names == {"dgemm_pipe<%d,%d%s" % (bm, bn, tag) for bm, bn in ((64, 128), (64, 64), (128, 64))}
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
     opA = np.swapaxes(A, 1, 2) if ta else A
