@@ -284,7 +284,10 @@ def bench_gemm_classes(args):
     """The two GEMM classes that dominate the solve, alone: a rank-256 update
     C -= A B (12288 x 6144 x 256, batch 8, Cin = C; the trailing updates of
     the factorisations) and an 8192^3 product (long k).  Prints the time and
-    rate of each (for counter runs under rocprofv3)."""
+    rate of each (for counter runs under rocprofv3), and beside them, as a
+    reference for what the FP64 matrix cores sustain, the same products
+    through torch (the vendor BLAS, row-major copies of the operands; not
+    part of the library's path)."""
     import ctypes
     import torch
     from paper_1806_06204_amd import zolo
@@ -311,7 +314,28 @@ def bench_gemm_classes(args):
         key = f"{m}x{n}x{k}x{b}" + ("_cin" if beta else "")
         out[key] = {"ms": dt * 1e3, "tflops": 2.0 * m * n * k * b / dt / 1e12}
         print(f"[bench] gemm {key}: {dt * 1e3:.3f} ms, {out[key]['tflops']:.1f} TFLOP/s", file=sys.stderr, flush=True)
+        Ar, Br = A.transpose(1, 2).contiguous(), B.transpose(1, 2).contiguous()
+        Cr = C.transpose(1, 2).contiguous()
         del A, B, C
+
+        def vendor():
+            if beta:
+                Cr.baddbmm_(Ar, Br, alpha=-1.0)
+            else:
+                torch.matmul(Ar, Br, out=Cr)
+        for _ in range(max(1, args.warmup)):
+            vendor()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            vendor()
+        torch.cuda.synchronize()
+        dv = (time.perf_counter() - t0) / args.steps
+        out[key]["vendor_ms"] = dv * 1e3
+        out[key]["vendor_tflops"] = 2.0 * m * n * k * b / dv / 1e12
+        print(f"[bench] vendor {key}: {dv * 1e3:.3f} ms, {out[key]['vendor_tflops']:.1f} TFLOP/s", file=sys.stderr,
+              flush=True)
+        del Ar, Br, Cr
     print(json.dumps({"gemm_classes": out}), flush=True)
     z.close()
 
