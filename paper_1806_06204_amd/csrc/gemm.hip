@@ -735,8 +735,9 @@ __global__ __launch_bounds__(256, 2) void dgemm_pipe_kernel(GemmDescT<double> d)
     using LA = Lay<BM, TA>;
     using LB = Lay<BN, !TB>;
     constexpr int NA = LA::kChunks * 2, NB = LB::kChunks * 2;   // doubles per slice
-    // Three LDS stages of A and B slices; after the k-loop the same memory
-    // holds the output tile for the coalesced epilogue.
+    // Room for three slices of A and of B: the k-loop uses two stages of
+    // each, and after it the same memory holds the output tile for the
+    // coalesced epilogue (the 64 x 128 tile needs the third slice's room).
     __shared__ __align__(16) double lds[3 * (NA + NB)];
     // Stage s: A slice at lds + s NA, B slice at lds + 3 NA + s NB.
     // Output tile in LDS, column-major with a padded leading dimension.
@@ -816,19 +817,19 @@ __global__ __launch_bounds__(256, 2) void dgemm_pipe_kernel(GemmDescT<double> d)
     // Each lane loads 16-byte chunks (two elements adjacent in memory) of
     // the slice into registers and later stores them to its slots of the
     // LDS layout.  The dispatcher only sends launches whose chunks are all
-    // 16-byte aligned and never straddle an edge (even extents along pairs,
-    // even leading dimensions and strides, even k for operands contiguous
-    // along k), so every slice issues the same loads from in-bounds
-    // addresses: rows of op(A) past m (columns of op(B) past n) are clamped
-    // to the last pair (they only reach outputs that are never stored), k
-    // past the slice's range is clamped to its last pair, and elements
-    // outside the k-range or the triangle of a triangular operand are set
-    // to zero in registers before the store.
+    // 16-byte aligned and never straddle an edge of op(A) or op(B) (even
+    // extents along pairs, even leading dimensions and strides), so every
+    // slice issues the same loads from in-bounds addresses: rows of op(A)
+    // past m (columns of op(B) past n) are clamped to the last pair (they
+    // only reach outputs that are never stored), a ragged last slice is
+    // shifted back to end at ke (below), and elements outside the slice's
+    // k-range or the triangle of a triangular operand are set to zero in
+    // registers before the store.
     constexpr int KA = LA::kPerWave, KB = LB::kPerWave;
     const int a_last = TA ? d.m - 1 : d.m - 2, b_last = TB ? d.n - 2 : d.n - 1;
     const long long ka = TA ? 1 : d.lda, kbs = TB ? d.ldb : 1;   // offset step per k
-    // Per chunk: element offset of its (clamped) row or column and its k
-    // within the slice, relative to the slice's first k.
+    // Per chunk: element offset of its (clamped) row or column at its k
+    // within the slice, relative to the slice's first element.
     long long dA[KA], dB[KB];
 #pragma unroll
     for (int q = 0; q < KA; ++q) {
@@ -855,7 +856,8 @@ __global__ __launch_bounds__(256, 2) void dgemm_pipe_kernel(GemmDescT<double> d)
     // Odd k with an operand contiguous along k: the pairs of the ragged last
     // slice would straddle the end of k, so that slice is taken after the
     // loop with element-wise loads (the dispatcher sends such products only
-    // as launches of one matrix, where it is the last of the sequence).
+    // in launches that do not sum over the batch, so the ragged slice ends
+    // the sequence of the workgroup that has it).
     const bool peel = (TA || !TB) && (ke & 1) && t_end == ntiles;
     const int t_main = peel ? t_end - 1 : t_end;   // end of the pipelined slices
 
