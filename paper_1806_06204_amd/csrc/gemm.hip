@@ -782,7 +782,6 @@ __global__ __launch_bounds__(256, 2) void dgemm_pipe_kernel(GemmDescT<double> d)
     const int z2 = split ? 0 : blockIdx.z;
     const int t_begin = split ? (int)((long long)blockIdx.z * ntiles / d.splitk) : 0;
     const int t_end = split ? (int)((long long)(blockIdx.z + 1) * ntiles / d.splitk) : ntiles;
-    const int nt = t_end - t_begin;
 
     d4 acc[FM][FN];
 #pragma unroll
